@@ -1,0 +1,65 @@
+"""Linearised single-mode update matrix (oracle, for the hydrodynamic pins).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Around a uniform rest state (eps0, u = (1,0,0,0)) a small perturbation
+dF ~ exp(i k.x) of the energy-momentum populations evolves, to first order,
+as dF(t+1) = M(k) dF(t) with
+
+    M(k) = [I - (1/tau) (I - E)] S(k)
+
+(stream, then collide: the state is the post-collision population),
+
+built here directly from the definitions, independently of `rlb.step`:
+
+* S(k) = diag(s_i(k)), the Fourier symbol of the bilinear pull of direction
+  i (Ch. 3, linear interpolation of off-lattice streaming);
+* the Anderson-Witting rate (u^0 - u.v_i)/tau is 1/tau at rest; its
+  perturbation multiplies F - F_eq, which vanishes at rest;
+* E is the linearised equilibrium: d(F_eq,i) = w_i (dT^{00} + 3 v_i.dT^{0.})
+  because the second-order coefficient (15/2)(T_eq^{kl} - delta^{kl}
+  T_eq^{00}/3) is quadratic in u (Ch. 3, eqs. stressEnergyT, rel_pdf_exp_coef).
+"""
+import numpy as np
+
+from .velocity_set import velocity_set
+
+
+def stream_symbol(k, cfl=1.0):
+    """s_i(k) = sum over the 4 bilinear taps of weight * exp(-i k.offset)."""
+    v, _, _ = velocity_set()
+    s = np.zeros(v.shape[0], np.complex128)
+    for i in range(v.shape[0]):
+        dx, dy = cfl * v[i, 0], cfl * v[i, 1]
+        sx, sy = np.sign(dx), np.sign(dy)
+        ax, ay = abs(dx), abs(dy)
+        ex = np.exp(-1j * k[0] * sx)
+        ey = np.exp(-1j * k[1] * sy)
+        s[i] = ((1 - ax) + ax * ex) * ((1 - ay) + ay * ey)
+    return s
+
+
+def update_matrix(k, tau, cfl=1.0):
+    v, w, _ = velocity_set()
+    q = v.shape[0]
+    E = w[:, None] * (1.0 + 3.0 * v @ v.T)            # E_ij = w_i (1 + 3 v_i.v_j)
+    C = np.eye(q) - (np.eye(q) - E) / tau
+    return C @ np.diag(stream_symbol(k, cfl))
+
+
+def hydrodynamic_modes(k, tau, cfl=1.0):
+    """Return (lambda_shear, lambda_sound) for a wavevector k.  The shear mode
+    is the eigenvector with the largest transverse momentum weight, the sound
+    mode the one (Im lambda > 0) with the largest energy weight."""
+    v, _, _ = velocity_set()
+    M = update_matrix(k, tau, cfl)
+    lam, vec = np.linalg.eig(M)
+    kh = np.array([k[0], k[1], 0.0]) / np.linalg.norm(k)
+    th = np.array([-kh[1], kh[0], 0.0])
+    trans = np.abs(vec.T @ (v @ th))                  # |sum_i dF_i v_i.t|
+    energy = np.abs(vec.sum(axis=0))                  # |sum_i dF_i|
+    norm = np.linalg.norm(vec, axis=0)
+    i_shear = int(np.argmax(trans / norm * (np.abs(lam) > 0.5)))
+    cand = (lam.imag > 0) & (np.abs(lam) > 0.5)
+    i_sound = int(np.argmax(energy / norm * cand))
+    return lam[i_shear], lam[i_sound]
