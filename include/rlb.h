@@ -1,0 +1,220 @@
+/*
+ * rlb.h -- C ABI of librlb, an MI355X (gfx950) implementation of the
+ * relativistic lattice-Boltzmann (RLB) time step of Watson, "Turbulence in
+ * Two-Dimensional Relativistic Hydrodynamic Systems with a Lattice Boltzmann
+ * Model" (arXiv:2205.04658).
+ *
+ * The step (Ch. 3 "The Standard/Classical LBM" procedure with the
+ * relativistic pieces of Ch. 3 "Relativistic Lattice Boltzmann" and
+ * "Boltzmann to Lattice Boltzmann", the driving term of Ch. 4 eq. forceTerm
+ * and the impurity bounce-back of Ch. 5 "Model and Methods") is:
+ *   pull-stream with bilinear interpolation -> moments T^{mu nu}, J^mu ->
+ *   Landau matching (eps, u^mu), n = u_mu J^mu -> truncated Juttner
+ *   equilibrium -> Anderson-Witting relaxation + projected driving term
+ *   (body force + random k-shell stirring) -> bounce-back at solid nodes.
+ *
+ * Conventions
+ *   - Every pointer named d_* is device memory on the lattice's device;
+ *     h_* is host memory.  Device pointers must be 256-byte aligned.
+ *   - The library never allocates device memory: the caller passes one
+ *     workspace of rlb_workspace_bytes() bytes to rlb_create and keeps it
+ *     alive until rlb_destroy (which never frees it).
+ *   - All device work is enqueued on the stream given at creation (a
+ *     hipStream_t passed as void*, NULL = the null stream).  Calls that
+ *     return data to the host (rlb_conserved, rlb_sync, rlb_get_status)
+ *     synchronise that stream.
+ *   - Fields are float32 arrays [ny][nx], x fastest.
+ *   - Errors are status codes; nothing is thrown across the ABI.  Argument
+ *     checks happen before any device work and nothing is written when they
+ *     fail (RLB_EINVAL).  Device-side failures (a node with no timelike
+ *     Landau frame, a non-finite population) set a sticky flag that the next
+ *     synchronising call reports (RLB_ELANDAU / RLB_ENONFINITE).
+ *     rlb_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef RLB_H
+#define RLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RLB_OK = 0,
+  RLB_EINVAL = 1,       /* bad argument (shape, range, null, alignment)     */
+  RLB_EDEVICE = 2,      /* HIP runtime error or no usable gfx950 device      */
+  RLB_ENOMEM = 3,       /* workspace or buffer too small                     */
+  RLB_ENONFINITE = 4,   /* a population became non-finite                    */
+  RLB_ELANDAU = 5,      /* Landau matching found no timelike frame           */
+  RLB_ESTATE = 6,       /* state buffer has the wrong header / shape         */
+  RLB_EUNSUPPORTED = 7  /* valid request outside what the library implements */
+} rlb_status;
+
+/* rlb_params.flags */
+#define RLB_WALLS_Y 0x1u  /* rows y = 0 and y = ny-1 are solid (channel)      */
+#define RLB_FULL26  0x2u  /* store all 26 populations per family instead of  */
+                          /* the 17 z-mirror-folded planes (see rlb_create)   */
+
+/* Lattice parameters.
+ *   nx, ny   lattice nodes (one z node); 4 <= nx, ny; nx*ny < 2^31.
+ *   tau      relaxation time in time steps, tau > 1/2 (Ch. 3: eta =
+ *            tau_R (eps + P) / 5; the scheme's shear viscosity is
+ *            (tau - 1/2)/5 + nu_interp).
+ *   cfl      dt/dx in (0, 1]; populations move cfl * (v_x, v_y) per step.
+ *   flags    RLB_WALLS_Y | RLB_FULL26.
+ *   eps_ref, n_ref  shifted-storage references: populations are stored as
+ *            F_i - w_i eps_ref and G_i - w_i n_ref in float32 (the float32
+ *            rounding then acts on the deviation only).  Any finite value is
+ *            valid; the mean of the initial fields is the best choice.
+ */
+typedef struct {
+  int32_t nx, ny;
+  double tau;
+  double cfl;
+  uint32_t flags;
+  double eps_ref;
+  double n_ref;
+} rlb_params;
+
+typedef struct rlb_lattice rlb_lattice;   /* opaque, host heap */
+
+/* Field identifiers for rlb_read_fields (bit k of field_mask = field k).
+ * Fields are those of the current state: the populations are streamed, then
+ * moments and Landau matching are taken, with no collision (Ch. 3 LBM
+ * procedure, step 3).  Solid nodes report 0. */
+enum {
+  RLB_FIELD_EPS = 0,     /* Landau energy density eps                      */
+  RLB_FIELD_BETA_X = 1,  /* 3-velocity u^x / u^0                            */
+  RLB_FIELD_BETA_Y = 2,
+  RLB_FIELD_N = 3,       /* charge density n = u_mu J^mu                    */
+  RLB_FIELD_T00 = 4, RLB_FIELD_T0X = 5, RLB_FIELD_T0Y = 6,
+  RLB_FIELD_TXX = 7, RLB_FIELD_TXY = 8, RLB_FIELD_TYY = 9,
+  RLB_FIELD_J0 = 10, RLB_FIELD_JX = 11, RLB_FIELD_JY = 12,
+  RLB_FIELD_COUNT = 13
+};
+
+/* Bytes of workspace a lattice with these parameters needs. */
+rlb_status rlb_workspace_bytes(const rlb_params* p, size_t* bytes);
+
+/* Create a lattice on the current HIP device.  The state is undefined until
+ * rlb_init_fields or rlb_load_state.  Populations are stored per family as
+ * planes [i][ny][nx]: 17 planes by default -- the 26 directions of the
+ * momentum set with each z-mirror pair (v_x, v_y, +v_z) / (v_x, v_y, -v_z)
+ * folded into one plane holding the pair's sum, which is exact because the
+ * lattice has one z node and no z force, so mirror populations stay equal --
+ * or 26 planes with RLB_FULL26.  Errors: RLB_EINVAL (params, pointer,
+ * alignment), RLB_ENOMEM (bytes too small), RLB_EDEVICE (not gfx950). */
+rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
+                      void* hip_stream, rlb_lattice** out);
+
+/* Release the handle.  Does not free the workspace.  NULL is a no-op. */
+rlb_status rlb_destroy(rlb_lattice* lat);
+
+/* F = F_eq(eps, u), G = G_eq(n, u) at every node, u^mu = gamma (1, beta)
+ * (Ch. 3 LBM procedure step 1).  Resets the step counter to 0.
+ * d_eps, d_bx, d_by, d_n: float32 [ny][nx]; eps > 0, bx^2 + by^2 < 1
+ * (violations raise the device flag, reported as RLB_ELANDAU). */
+rlb_status rlb_init_fields(rlb_lattice* lat, const float* d_eps,
+                           const float* d_bx, const float* d_by,
+                           const float* d_n);
+
+/* Mark solid (bounce-back) nodes: every nonzero byte of d_mask [ny][nx]
+ * becomes solid, in addition to walls and discs already set. */
+rlb_status rlb_set_obstacles(rlb_lattice* lat, const uint8_t* d_mask);
+
+/* Add discs (Ch. 5 impurities): node (x, y) is solid when dx^2 + dy^2 <= r^2
+ * with dx, dy the periodic minimum-image distances to the centre.
+ * h_cx_cy_r: host array of count triples (cx, cy, r), r > 0, finite. */
+rlb_status rlb_add_disks(rlb_lattice* lat, int32_t count,
+                         const double* h_cx_cy_r);
+
+/* Remove every obstacle except the RLB_WALLS_Y rows. */
+rlb_status rlb_clear_obstacles(rlb_lattice* lat);
+
+/* Uniform body force (F^x, F^y) added to the stirring force in the driving
+ * term of every fluid node (Ch. 4 eq. forceTerm with T_0 = 1). */
+rlb_status rlb_set_body_force(rlb_lattice* lat, double fx, double fy);
+
+/* Random k-shell stirring (Ch. 4 "Model and Methods"): every step, each
+ * integer mode kmin <= |k| <= kmax on the half plane (ky > 0 or ky = 0,
+ * kx > 0; ordered by ky then kx, index m) gets complex coefficients
+ *   Fx_hat = amplitude (z0 + i z1),  Fy_hat = amplitude (z2 + i z3)
+ * where z0..z3 are Box-Muller normals from the Philox4x64-10 block with
+ * counter (m, step, 0, 0) and key (seed, 0); the conjugate fills -k and the
+ * real-space force is F_c(x,y) = sum_shell F_c_hat e^{2 pi i (kx x/nx +
+ * ky y/ny)}.  amplitude = 0 disables stirring.  0 <= kmin <= kmax <= 63,
+ * kmax < min(nx, ny) / 2, at least one mode in the shell. */
+rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax,
+                            double amplitude, uint64_t seed);
+
+/* Advance nsteps >= 0 steps (asynchronous on the stream). */
+rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps);
+
+/* Write the fields selected by field_mask (bits of RLB_FIELD_*) to d_out as
+ * consecutive float32 planes [k][ny][nx] in increasing field order. */
+rlb_status rlb_read_fields(rlb_lattice* lat, uint32_t field_mask, float* d_out);
+
+/* Global totals over all nodes of the current (post-collision) state:
+ * h_out = {E = sum F, P^x = sum F v_x, P^y = sum F v_y, Q = sum G}, summed
+ * in float64 in a fixed order (deterministic).  Synchronises. */
+rlb_status rlb_conserved(rlb_lattice* lat, double h_out[4]);
+
+/* Wait for queued work; report sticky device failures. */
+rlb_status rlb_sync(rlb_lattice* lat);
+
+/* Number of steps taken since rlb_init_fields / rlb_load_state. */
+rlb_status rlb_get_step(const rlb_lattice* lat, int64_t* step);
+
+/* Bytes of a saved state (header + raw float32 planes). */
+rlb_status rlb_state_bytes(const rlb_lattice* lat, size_t* bytes);
+
+/* Copy the state (raw shifted float32 planes, step counter, parameters) to
+ * d_buf / restore it.  A save followed by a load and N steps is bitwise
+ * identical to N steps.  Load checks the header (RLB_ESTATE on mismatch). */
+rlb_status rlb_save_state(rlb_lattice* lat, void* d_buf, size_t bytes);
+rlb_status rlb_load_state(rlb_lattice* lat, const void* d_buf, size_t bytes);
+
+/* Number of population planes per family (17 or 26) and the plane pitch in
+ * elements used in saved states (planes start at header + k * pitch * 4). */
+rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int64_t* pitch,
+                      size_t* header_bytes);
+
+/* Stirring coefficients of a given step without advancing anything:
+ * d_out[4m .. 4m+3] = (Re Fx_hat, Im Fx_hat, Re Fy_hat, Im Fy_hat) of mode
+ * m, float64.  *count receives the number of half-shell modes. */
+rlb_status rlb_stirring_coefficients(rlb_lattice* lat, int64_t step,
+                                     double* d_out, int32_t* count);
+
+/* The real-space stirring field of a given step, float32 [2][ny][nx]
+ * (F^x then F^y), evaluated exactly as the step evaluates it. */
+rlb_status rlb_stirring_field(rlb_lattice* lat, int64_t step, float* d_out);
+
+/* Raw Philox4x64-10 blocks: d_out[4m + j] = word j of the block with
+ * counter (m, c1, 0, 0) and key (k0, k1), m < count.  For testing the
+ * generator bit for bit. */
+rlb_status rlb_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count,
+                      uint64_t* d_out, void* hip_stream);
+
+/* Per-launch timing of the main step kernel with HIP events on the lattice
+ * stream.  rlb_timing(lat, 1) starts recording (and clears totals);
+ * rlb_timing_read synchronises and returns the summed kernel time in ms and
+ * the number of timed launches. */
+rlb_status rlb_timing(rlb_lattice* lat, int32_t enable);
+rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches);
+
+/* A plain device copy of `bytes` (multiple of 16) for bandwidth calibration. */
+rlb_status rlb_copy_probe(const void* d_src, void* d_dst, size_t bytes,
+                          void* hip_stream);
+
+/* Human-readable message of the last failure on this thread. */
+const char* rlb_last_error(void);
+
+/* Library version string. */
+const char* rlb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLB_H */

@@ -1,0 +1,567 @@
+// librlb C ABI: argument validation, workspace layout, launch sequencing and
+// error state.  Every device action is enqueued on the lattice's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dirset.hpp"
+#include "internal.hpp"
+
+using namespace rlb;
+
+namespace {
+
+thread_local std::string g_err;
+
+rlb_status fail(rlb_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+rlb_status hip_fail(hipError_t e, const char* what) {
+  return fail(RLB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+constexpr uint64_t kMagic = 0x4554415453424C52ull;   // "RLBSTATE"
+constexpr size_t kHeaderBytes = 256;
+
+struct StateHeader {
+  uint64_t magic;
+  int32_t version, nx, ny, q;
+  int64_t pitch, step;
+  double eps_ref, n_ref, tau, cfl;
+  uint32_t flags;
+};
+
+rlb_status check_params(const rlb_params* p) {
+  if (!p) return fail(RLB_EINVAL, "params is null");
+  if (p->nx < 4 || p->ny < 4) return fail(RLB_EINVAL, "nx, ny must be >= 4 (got %d x %d)", p->nx, p->ny);
+  if ((int64_t)p->nx * p->ny >= (int64_t)1 << 31)
+    return fail(RLB_EINVAL, "nx * ny must be < 2^31");
+  if (!std::isfinite(p->tau) || !(p->tau > 0.5)) return fail(RLB_EINVAL, "tau must be finite and > 1/2");
+  if (!std::isfinite(p->cfl) || !(p->cfl > 0.0) || p->cfl > 1.0)
+    return fail(p->cfl > 1.0 && std::isfinite(p->cfl) ? RLB_EUNSUPPORTED : RLB_EINVAL,
+                "cfl must be in (0, 1] (bilinear pull over a one-node neighbourhood)");
+  if (p->flags & ~(RLB_WALLS_Y | RLB_FULL26)) return fail(RLB_EINVAL, "unknown flags 0x%x", p->flags);
+  if (!std::isfinite(p->eps_ref) || !std::isfinite(p->n_ref))
+    return fail(RLB_EINVAL, "eps_ref and n_ref must be finite");
+  return RLB_OK;
+}
+
+Workspace layout(const rlb_params* p, int Q, int64_t pitch) {
+  Workspace w;
+  size_t off = 0;
+  const size_t state = align_up((size_t)2 * Q * pitch * sizeof(float));
+  w.state_off[0] = off; off += state;
+  w.state_off[1] = off; off += state;
+  w.mask_off = off; off += align_up((size_t)p->nx * p->ny);
+  w.coef_off = off; off += align_up((size_t)kMaxModes * 4 * sizeof(double));
+  w.modes_off = off; off += align_up((size_t)kMaxModes * sizeof(int4));
+  w.bins_off = off; off += align_up((size_t)(kMaxK + 2) * sizeof(int32_t));
+  w.table_off = off; off += align_up((size_t)p->ny * (kMaxK + 1) * sizeof(float4));
+  w.partial_off = off; off += align_up((size_t)kRedBlocks * 4 * sizeof(double));
+  w.misc_off = off; off += align_up(256);
+  w.total = off;
+  return w;
+}
+
+int planes_of(const rlb_params* p) { return (p->flags & RLB_FULL26) ? 26 : 17; }
+
+// Bilinear tap weights per plane, quantised to multiples of 2^-24 with the
+// last weight taking the exact remainder, so the four float32 weights sum to
+// exactly 1 and streaming does not scale a plane's total.
+template <class DS>
+void fill_taps(rlb_lattice* lat) {
+  const double q = 16777216.0;   // 2^24
+  for (int k = 0; k < DS::Q; ++k) {
+    const double ax = lat->p.cfl * std::fabs(DS::vx[k]);
+    const double ay = lat->p.cfl * std::fabs(DS::vy[k]);
+    const double w00 = std::nearbyint((1 - ax) * (1 - ay) * q) / q;
+    const double w10 = std::nearbyint(ax * (1 - ay) * q) / q;
+    const double w01 = std::nearbyint((1 - ax) * ay * q) / q;
+    const double w11 = 1.0 - w00 - w10 - w01;     // exact: multiples of 2^-24
+    lat->tap[k][0] = (float)w00;
+    lat->tap[k][1] = (float)w10;
+    lat->tap[k][2] = (float)w01;
+    lat->tap[k][3] = (float)w11;
+  }
+}
+
+rlb_status check_lat(const rlb_lattice* lat) {
+  if (!lat) return fail(RLB_EINVAL, "lattice is null");
+  return RLB_OK;
+}
+
+StirArgs stir_args(const rlb_lattice* lat) {
+  StirArgs a;
+  a.modes = lat->modes;
+  a.bins = lat->bins;
+  a.coef = lat->coef;
+  a.table = lat->table;
+  a.dstep = lat->dstep;
+  a.nmodes = lat->nmodes;
+  a.K = lat->K;
+  a.nx = lat->p.nx;
+  a.ny = lat->p.ny;
+  a.amplitude = lat->amp;
+  a.seed = lat->seed;
+  a.stream = 0;
+  return a;
+}
+
+rlb_status read_err(rlb_lattice* lat) {
+  uint32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, lat->err, sizeof h, hipMemcpyDeviceToHost, lat->stream), "read error flag");
+  HIP_TRY(hipStreamSynchronize(lat->stream), "stream synchronize");
+  if (h & ERR_LANDAU) return fail(RLB_ELANDAU, "a fluid node had no timelike Landau frame (step %lld)", (long long)lat->step);
+  if (h & ERR_NONFINITE) return fail(RLB_ENONFINITE, "a population became non-finite (step %lld)", (long long)lat->step);
+  return RLB_OK;
+}
+
+constexpr int kEvRing = 16;
+
+// Fold the elapsed time of pending event pair i into the totals.
+rlb_status drain_event(rlb_lattice* lat, int i) {
+  if (!(lat->ev_pending & (1u << i))) return RLB_OK;
+  HIP_TRY(hipEventSynchronize(lat->ev[i][1]), "event synchronize");
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, lat->ev[i][0], lat->ev[i][1]), "event elapsed");
+  lat->timed_ms += ms;
+  lat->timed_launches += 1;
+  lat->ev_pending &= ~(1u << i);
+  return RLB_OK;
+}
+
+rlb_status accumulate_timing(rlb_lattice* lat) {
+  for (int i = 0; i < kEvRing; ++i)
+    if (rlb_status s = drain_event(lat, i)) return s;
+  return RLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rlb_last_error(void) { return g_err.c_str(); }
+
+const char* rlb_version(void) { return "librlb 0.1 (gfx950)"; }
+
+rlb_status rlb_workspace_bytes(const rlb_params* p, size_t* bytes) {
+  rlb_status s = check_params(p);
+  if (s) return s;
+  if (!bytes) return fail(RLB_EINVAL, "bytes is null");
+  const int Q = planes_of(p);
+  const int64_t pitch = (int64_t)align_up((size_t)p->nx * p->ny, 64);
+  *bytes = layout(p, Q, pitch).total;
+  return RLB_OK;
+}
+
+rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
+                      void* hip_stream, rlb_lattice** out) {
+  rlb_status s = check_params(p);
+  if (s) return s;
+  if (!out) return fail(RLB_EINVAL, "out is null");
+  *out = nullptr;
+  if (!d_workspace || !aligned(d_workspace, kAlign))
+    return fail(RLB_EINVAL, "workspace must be a non-null 256-byte aligned device pointer");
+  const int Q = planes_of(p);
+  const int64_t pitch = (int64_t)align_up((size_t)p->nx * p->ny, 64);
+  const Workspace w = layout(p, Q, pitch);
+  if (bytes < w.total) return fail(RLB_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, w.total);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "no HIP device");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "device properties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(RLB_EDEVICE, "device %d is %s; librlb is built for gfx950", dev, prop.gcnArchName);
+  hipPointerAttribute_t attr;
+  e = hipPointerGetAttributes(&attr, d_workspace);
+  if (e != hipSuccess || attr.type != hipMemoryTypeDevice)
+    return fail(RLB_EINVAL, "workspace is not device memory");
+
+  rlb_lattice* lat = new (std::nothrow) rlb_lattice();
+  if (!lat) return fail(RLB_ENOMEM, "host allocation failed");
+  lat->p = *p;
+  lat->device = dev;
+  lat->stream = (hipStream_t)hip_stream;
+  lat->Q = Q;
+  lat->pitch = pitch;
+  lat->ws = (char*)d_workspace;
+  lat->ws_bytes = bytes;
+  lat->lay = w;
+  lat->state[0] = (float*)(lat->ws + w.state_off[0]);
+  lat->state[1] = (float*)(lat->ws + w.state_off[1]);
+  lat->cur = 0;
+  lat->mask = (uint8_t*)(lat->ws + w.mask_off);
+  lat->coef = (double*)(lat->ws + w.coef_off);
+  lat->modes = (int4*)(lat->ws + w.modes_off);
+  lat->bins = (int32_t*)(lat->ws + w.bins_off);
+  lat->table = (float4*)(lat->ws + w.table_off);
+  lat->partials = (double*)(lat->ws + w.partial_off);
+  lat->err = (uint32_t*)(lat->ws + w.misc_off);
+  lat->dstep = (int64_t*)(lat->ws + w.misc_off + 64);
+  lat->result = (double*)(lat->ws + w.misc_off + 128);
+  if (Q == 17) fill_taps<Dir17>(lat); else fill_taps<Dir26>(lat);
+
+  rlb_status st = RLB_OK;
+  e = launch_fill_u8(lat->mask, (size_t)p->nx * p->ny, 0, lat->stream);
+  if (e == hipSuccess) e = launch_fill_u8((uint8_t*)lat->err, 64, 0, lat->stream);
+  if (e == hipSuccess) e = launch_set_i64(lat->dstep, 0, lat->stream);
+  if (e == hipSuccess && (p->flags & RLB_WALLS_Y)) {
+    e = launch_walls(lat);
+    lat->any_solid = true;
+  }
+  if (e != hipSuccess) st = hip_fail(e, "workspace initialisation");
+  if (st) {
+    delete lat;
+    return st;
+  }
+  *out = lat;
+  return RLB_OK;
+}
+
+rlb_status rlb_destroy(rlb_lattice* lat) {
+  if (!lat) return RLB_OK;
+  if (lat->ev[0][0]) {
+    for (int i = 0; i < kEvRing; ++i)
+      for (int j = 0; j < 2; ++j)
+        if (lat->ev[i][j]) (void)hipEventDestroy(lat->ev[i][j]);
+  }
+  delete lat;
+  return RLB_OK;
+}
+
+rlb_status rlb_init_fields(rlb_lattice* lat, const float* d_eps, const float* d_bx,
+                           const float* d_by, const float* d_n) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!d_eps || !d_bx || !d_by || !d_n) return fail(RLB_EINVAL, "field pointers must be non-null");
+  if (!aligned(d_eps, 4) || !aligned(d_bx, 4) || !aligned(d_by, 4) || !aligned(d_n, 4))
+    return fail(RLB_EINVAL, "field pointers must be 4-byte aligned");
+  HIP_TRY(launch_fill_u8((uint8_t*)lat->err, 64, 0, lat->stream), "clear error flag");
+  lat->cur = 0;
+  HIP_TRY(launch_init(lat, d_eps, d_bx, d_by, d_n, lat->state[0]), "init kernel");
+  lat->step = 0;
+  HIP_TRY(launch_set_i64(lat->dstep, 0, lat->stream), "step counter");
+  return RLB_OK;
+}
+
+rlb_status rlb_set_obstacles(rlb_lattice* lat, const uint8_t* d_mask) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!d_mask) return fail(RLB_EINVAL, "mask is null");
+  HIP_TRY(launch_mask_or(lat, d_mask), "mask kernel");
+  lat->any_solid = true;
+  return RLB_OK;
+}
+
+rlb_status rlb_add_disks(rlb_lattice* lat, int32_t count, const double* h) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (count < 0) return fail(RLB_EINVAL, "count must be >= 0");
+  if (count > 0 && !h) return fail(RLB_EINVAL, "disc array is null");
+  for (int i = 0; i < count; ++i) {
+    if (!std::isfinite(h[3 * i]) || !std::isfinite(h[3 * i + 1]) || !std::isfinite(h[3 * i + 2]) ||
+        !(h[3 * i + 2] > 0.0))
+      return fail(RLB_EINVAL, "disc %d: centre must be finite and radius > 0", i);
+  }
+  // stage through the coefficient area of the workspace, in chunks
+  const int chunk = (int)(kMaxModes * 4 / 3);
+  for (int b = 0; b < count; b += chunk) {
+    const int n = std::min(chunk, count - b);
+    HIP_TRY(hipMemcpyAsync(lat->coef, h + 3 * (size_t)b, sizeof(double) * 3 * n,
+                           hipMemcpyHostToDevice, lat->stream), "upload discs");
+    HIP_TRY(launch_disks(lat, lat->coef, n), "disc kernel");
+    HIP_TRY(hipStreamSynchronize(lat->stream), "stream synchronize");
+  }
+  if (count > 0) lat->any_solid = true;
+  return RLB_OK;
+}
+
+rlb_status rlb_clear_obstacles(rlb_lattice* lat) {
+  if (rlb_status s = check_lat(lat)) return s;
+  HIP_TRY(launch_fill_u8(lat->mask, (size_t)lat->p.nx * lat->p.ny, 0, lat->stream), "clear mask");
+  lat->any_solid = false;
+  if (lat->p.flags & RLB_WALLS_Y) {
+    HIP_TRY(launch_walls(lat), "walls");
+    lat->any_solid = true;
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_set_body_force(rlb_lattice* lat, double fx, double fy) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!std::isfinite(fx) || !std::isfinite(fy)) return fail(RLB_EINVAL, "force must be finite");
+  lat->fx = fx;
+  lat->fy = fy;
+  return RLB_OK;
+}
+
+rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax, double amplitude,
+                            uint64_t seed) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!std::isfinite(amplitude) || amplitude < 0.0) return fail(RLB_EINVAL, "amplitude must be finite and >= 0");
+  if (amplitude == 0.0) {
+    lat->stir = false;
+    lat->amp = 0.0;
+    return RLB_OK;
+  }
+  if (!std::isfinite(kmin) || !std::isfinite(kmax) || kmin < 0.0 || kmin > kmax)
+    return fail(RLB_EINVAL, "need 0 <= kmin <= kmax");
+  if (kmax > (double)kMaxK) return fail(RLB_EUNSUPPORTED, "kmax must be <= %d", kMaxK);
+  if (kmax >= 0.5 * std::min(lat->p.nx, lat->p.ny))
+    return fail(RLB_EINVAL, "kmax must be below min(nx, ny) / 2");
+  // canonical half-shell order: ky ascending, then kx ascending
+  std::vector<int4> modes;
+  const int K = (int)std::floor(kmax);
+  for (int ky = 0; ky <= K; ++ky)
+    for (int kx = -K; kx <= K; ++kx) {
+      if (ky == 0 && kx <= 0) continue;
+      const double k2 = (double)kx * kx + (double)ky * ky;
+      if (k2 >= kmin * kmin && k2 <= kmax * kmax)
+        modes.push_back(make_int4((int)modes.size(), kx, ky, 0));
+    }
+  if (modes.empty()) return fail(RLB_EINVAL, "the shell [%g, %g] holds no integer mode", kmin, kmax);
+  if ((int)modes.size() > kMaxModes) return fail(RLB_EUNSUPPORTED, "too many modes");
+  int kmaxx = 0;
+  for (auto& m : modes) kmaxx = std::max(kmaxx, std::abs(m.y));
+  // bins by |kx|, modes in canonical order inside a bin
+  std::vector<int4> binned;
+  std::vector<int32_t> bins(kMaxK + 2, 0);
+  for (int k = 0; k <= kmaxx; ++k) {
+    bins[k] = (int32_t)binned.size();
+    for (auto& m : modes)
+      if (std::abs(m.y) == k) binned.push_back(m);
+  }
+  for (int k = kmaxx + 1; k <= kMaxK + 1; ++k) bins[k] = (int32_t)binned.size();
+  HIP_TRY(hipMemcpyAsync(lat->modes, binned.data(), sizeof(int4) * binned.size(),
+                         hipMemcpyHostToDevice, lat->stream), "upload modes");
+  HIP_TRY(hipMemcpyAsync(lat->bins, bins.data(), sizeof(int32_t) * bins.size(),
+                         hipMemcpyHostToDevice, lat->stream), "upload bins");
+  HIP_TRY(hipStreamSynchronize(lat->stream), "stream synchronize");
+  lat->stir = true;
+  lat->kmin = kmin;
+  lat->kmax = kmax;
+  lat->amp = amplitude;
+  lat->seed = seed;
+  lat->nmodes = (int)modes.size();
+  lat->K = kmaxx;
+  HIP_TRY(launch_set_i64(lat->dstep, lat->step, lat->stream), "step counter");
+  return RLB_OK;
+}
+
+rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (nsteps < 0) return fail(RLB_EINVAL, "nsteps must be >= 0");
+  const int force = lat->stir ? FORCE_STIR : ((lat->fx != 0.0 || lat->fy != 0.0) ? FORCE_BODY : FORCE_NONE);
+  const StirArgs sa = stir_args(lat);
+  for (int64_t t = 0; t < nsteps; ++t) {
+    if (lat->stir) {
+      HIP_TRY(launch_stir_draw(sa, -1, lat->stream), "stirring draw");
+      HIP_TRY(launch_stir_table(sa, lat->stream), "stirring table");
+    }
+    int slot = 0;
+    if (lat->timing) {
+      slot = (int)(lat->step % kEvRing);
+      if (rlb_status s = drain_event(lat, slot)) return s;
+      HIP_TRY(hipEventRecord(lat->ev[slot][0], lat->stream), "event record");
+    }
+    HIP_TRY(launch_step(lat, MODE_STEP, force, lat->state[lat->cur], lat->state[lat->cur ^ 1],
+                        nullptr, 0), "step kernel");
+    if (lat->timing) {
+      HIP_TRY(hipEventRecord(lat->ev[slot][1], lat->stream), "event record");
+      lat->ev_pending |= 1u << slot;
+    }
+    lat->cur ^= 1;
+    lat->step += 1;
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_read_fields(rlb_lattice* lat, uint32_t field_mask, float* d_out) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (field_mask == 0 || field_mask >= (1u << RLB_FIELD_COUNT))
+    return fail(RLB_EINVAL, "field_mask must select fields 0..%d", RLB_FIELD_COUNT - 1);
+  if (!d_out || !aligned(d_out, 4)) return fail(RLB_EINVAL, "output must be a 4-byte aligned device pointer");
+  HIP_TRY(launch_step(lat, MODE_FIELDS, FORCE_NONE, lat->state[lat->cur], nullptr, d_out, field_mask),
+          "fields kernel");
+  return RLB_OK;
+}
+
+rlb_status rlb_conserved(rlb_lattice* lat, double h_out[4]) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!h_out) return fail(RLB_EINVAL, "output is null");
+  HIP_TRY(launch_totals(lat, lat->state[lat->cur], lat->result), "totals kernel");
+  double tmp[4];
+  HIP_TRY(hipMemcpyAsync(tmp, lat->result, sizeof tmp, hipMemcpyDeviceToHost, lat->stream), "read totals");
+  if (rlb_status s = read_err(lat)) return s;
+  std::memcpy(h_out, tmp, sizeof tmp);
+  return RLB_OK;
+}
+
+rlb_status rlb_sync(rlb_lattice* lat) {
+  if (rlb_status s = check_lat(lat)) return s;
+  return read_err(lat);
+}
+
+rlb_status rlb_get_step(const rlb_lattice* lat, int64_t* step) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!step) return fail(RLB_EINVAL, "step is null");
+  *step = lat->step;
+  return RLB_OK;
+}
+
+rlb_status rlb_state_bytes(const rlb_lattice* lat, size_t* bytes) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!bytes) return fail(RLB_EINVAL, "bytes is null");
+  *bytes = kHeaderBytes + (size_t)2 * lat->Q * lat->pitch * sizeof(float);
+  return RLB_OK;
+}
+
+rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int64_t* pitch, size_t* header_bytes) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (planes) *planes = lat->Q;
+  if (pitch) *pitch = lat->pitch;
+  if (header_bytes) *header_bytes = kHeaderBytes;
+  return RLB_OK;
+}
+
+rlb_status rlb_save_state(rlb_lattice* lat, void* d_buf, size_t bytes) {
+  if (rlb_status s = check_lat(lat)) return s;
+  size_t need = 0;
+  rlb_state_bytes(lat, &need);
+  if (!d_buf || !aligned(d_buf, kAlign)) return fail(RLB_EINVAL, "buffer must be a 256-byte aligned device pointer");
+  if (bytes < need) return fail(RLB_ENOMEM, "state buffer has %zu bytes, needs %zu", bytes, need);
+  // the header staging area lives in the handle, so it outlives the copy
+  HIP_TRY(hipStreamSynchronize(lat->stream), "stream synchronize");
+  StateHeader h{};
+  h.magic = kMagic;
+  h.version = 1;
+  h.nx = lat->p.nx;
+  h.ny = lat->p.ny;
+  h.q = lat->Q;
+  h.pitch = lat->pitch;
+  h.step = lat->step;
+  h.eps_ref = lat->p.eps_ref;
+  h.n_ref = lat->p.n_ref;
+  h.tau = lat->p.tau;
+  h.cfl = lat->p.cfl;
+  h.flags = lat->p.flags;
+  std::memset(lat->header, 0, sizeof lat->header);
+  std::memcpy(lat->header, &h, sizeof h);
+  HIP_TRY(hipMemcpyAsync(d_buf, lat->header, kHeaderBytes, hipMemcpyHostToDevice, lat->stream), "write header");
+  HIP_TRY(hipMemcpyAsync((char*)d_buf + kHeaderBytes, lat->state[lat->cur],
+                         (size_t)2 * lat->Q * lat->pitch * sizeof(float),
+                         hipMemcpyDeviceToDevice, lat->stream), "copy state");
+  HIP_TRY(hipStreamSynchronize(lat->stream), "stream synchronize");
+  return RLB_OK;
+}
+
+rlb_status rlb_load_state(rlb_lattice* lat, const void* d_buf, size_t bytes) {
+  if (rlb_status s = check_lat(lat)) return s;
+  size_t need = 0;
+  rlb_state_bytes(lat, &need);
+  if (!d_buf || !aligned(d_buf, kAlign)) return fail(RLB_EINVAL, "buffer must be a 256-byte aligned device pointer");
+  if (bytes < need) return fail(RLB_ENOMEM, "state buffer has %zu bytes, needs %zu", bytes, need);
+  StateHeader h{};
+  HIP_TRY(hipMemcpyAsync(&h, d_buf, sizeof h, hipMemcpyDeviceToHost, lat->stream), "read header");
+  HIP_TRY(hipStreamSynchronize(lat->stream), "stream synchronize");
+  if (h.magic != kMagic || h.version != 1) return fail(RLB_ESTATE, "not an RLB state buffer");
+  if (h.nx != lat->p.nx || h.ny != lat->p.ny || h.q != lat->Q || h.pitch != lat->pitch ||
+      h.eps_ref != lat->p.eps_ref || h.n_ref != lat->p.n_ref)
+    return fail(RLB_ESTATE, "state shape or references differ from this lattice");
+  HIP_TRY(hipMemcpyAsync(lat->state[lat->cur], (const char*)d_buf + kHeaderBytes,
+                         (size_t)2 * lat->Q * lat->pitch * sizeof(float),
+                         hipMemcpyDeviceToDevice, lat->stream), "copy state");
+  HIP_TRY(launch_fill_u8((uint8_t*)lat->err, 64, 0, lat->stream), "clear error flag");
+  lat->step = h.step;
+  HIP_TRY(launch_set_i64(lat->dstep, lat->step, lat->stream), "step counter");
+  return RLB_OK;
+}
+
+rlb_status rlb_stirring_coefficients(rlb_lattice* lat, int64_t step, double* d_out, int32_t* count) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!lat->stir) return fail(RLB_EINVAL, "stirring is not set");
+  if (step < 0) return fail(RLB_EINVAL, "step must be >= 0");
+  if (!d_out || !aligned(d_out, 8)) return fail(RLB_EINVAL, "output must be an 8-byte aligned device pointer");
+  StirArgs a = stir_args(lat);
+  a.coef = d_out;
+  HIP_TRY(launch_stir_draw(a, step, lat->stream), "stirring draw");
+  if (count) *count = lat->nmodes;
+  return RLB_OK;
+}
+
+rlb_status rlb_stirring_field(rlb_lattice* lat, int64_t step, float* d_out) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!lat->stir) return fail(RLB_EINVAL, "stirring is not set");
+  if (step < 0) return fail(RLB_EINVAL, "step must be >= 0");
+  if (!d_out || !aligned(d_out, 4)) return fail(RLB_EINVAL, "output must be a 4-byte aligned device pointer");
+  const StirArgs a = stir_args(lat);
+  HIP_TRY(launch_stir_draw(a, step, lat->stream), "stirring draw");
+  HIP_TRY(launch_stir_table(a, lat->stream), "stirring table");
+  HIP_TRY(launch_stir_field(lat, d_out), "stirring field");
+  return RLB_OK;
+}
+
+rlb_status rlb_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count, uint64_t* d_out,
+                      void* hip_stream) {
+  if (count < 0) return fail(RLB_EINVAL, "count must be >= 0");
+  if (count > 0 && (!d_out || !aligned(d_out, 8))) return fail(RLB_EINVAL, "output must be an 8-byte aligned device pointer");
+  HIP_TRY(launch_philox(k0, k1, c1, count, d_out, (hipStream_t)hip_stream), "philox kernel");
+  return RLB_OK;
+}
+
+rlb_status rlb_timing(rlb_lattice* lat, int32_t enable) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (enable) {
+    if (!lat->ev[0][0]) {
+      for (int i = 0; i < kEvRing; ++i)
+        for (int j = 0; j < 2; ++j) HIP_TRY(hipEventCreate(&lat->ev[i][j]), "event create");
+    }
+    if (rlb_status s = accumulate_timing(lat)) return s;
+    lat->timed_ms = 0.0;
+    lat->timed_launches = 0;
+    lat->timing = true;
+  } else {
+    if (rlb_status s = accumulate_timing(lat)) return s;
+    lat->timing = false;
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (rlb_status s = accumulate_timing(lat)) return s;
+  if (total_ms) *total_ms = lat->timed_ms;
+  if (launches) *launches = lat->timed_launches;
+  return RLB_OK;
+}
+
+rlb_status rlb_copy_probe(const void* d_src, void* d_dst, size_t bytes, void* hip_stream) {
+  if (!d_src || !d_dst || !aligned(d_src, 16) || !aligned(d_dst, 16))
+    return fail(RLB_EINVAL, "copy probe needs 16-byte aligned device pointers");
+  if (bytes % 16) return fail(RLB_EINVAL, "bytes must be a multiple of 16");
+  HIP_TRY(launch_copy(d_src, d_dst, bytes, (hipStream_t)hip_stream), "copy kernel");
+  return RLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Conservation diagnostics: global E = sum F, P^x = sum F v_x,
+// P^y = sum F v_y, Q = sum G over all nodes (Ch. 2: d_mu T^{mu nu} = 0 and
+// charge conservation), in float64 with a fixed summation order: every
+// thread walks a fixed node set, wavefronts reduce with lane exchanges, the
+// workgroup through LDS, and one final workgroup sums the fixed number of
+// partials.  Also the plain copy kernel used to calibrate byte counters.
+#include "dirset.hpp"
+#include "internal.hpp"
+#include "device_common.hpp"
+
+namespace rlb {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <class DS>
+__global__ __launch_bounds__(256) void totals_kernel(const float* __restrict__ st,
+                                                     int64_t pitch, int ncell,
+                                                     double* partial) {
+  constexpr int Q = DS::Q;
+  double e = 0.0, px = 0.0, py = 0.0, q = 0.0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += stride) {
+    static_for<0, Q>([&](auto P) {
+      constexpr int p = decltype(P)::value;
+      const double f = (double)st[p * pitch + i];
+      e += f;
+      if constexpr (DS::vx[p] != 0.0) px += DS::vx[p] * f;
+      if constexpr (DS::vy[p] != 0.0) py += DS::vy[p] * f;
+      q += (double)st[(Q + p) * pitch + i];
+    });
+  }
+  __shared__ double red[4][4];
+  e = wave_sum(e);
+  px = wave_sum(px);
+  py = wave_sum(py);
+  q = wave_sum(q);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  if (ln == 0) {
+    red[wv][0] = e; red[wv][1] = px; red[wv][2] = py; red[wv][3] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    partial[4 * blockIdx.x + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+  }
+}
+
+__global__ __launch_bounds__(256) void totals_final_kernel(const double* __restrict__ partial,
+                                                           int nblocks, double ncell,
+                                                           double eps_ref, double n_ref,
+                                                           double* out) {
+  __shared__ double red[4][4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    for (int c = 0; c < 4; ++c) acc[c] += partial[4 * b + c];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int c = 0; c < 4; ++c) {
+    acc[c] = wave_sum(acc[c]);
+    if (ln == 0) red[wv][c] = acc[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    double v = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    if (c == 0) v += ncell * eps_ref;
+    if (c == 3) v += ncell * n_ref;
+    out[c] = v;
+  }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void copy_kernel(const f32x4* __restrict__ s,
+                                                   f32x4* __restrict__ d, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    __builtin_nontemporal_store(s[i], d + i);
+}
+
+hipError_t launch_totals(const rlb_lattice* lat, const float* state,
+                         double* result) {
+  const int ncell = lat->p.nx * lat->p.ny;
+  if (lat->Q == 17)
+    hipLaunchKernelGGL(totals_kernel<Dir17>, dim3(kRedBlocks), dim3(256), 0,
+                       lat->stream, state, lat->pitch, ncell, lat->partials);
+  else
+    hipLaunchKernelGGL(totals_kernel<Dir26>, dim3(kRedBlocks), dim3(256), 0,
+                       lat->stream, state, lat->pitch, ncell, lat->partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, lat->stream,
+                     lat->partials, kRedBlocks, (double)ncell, lat->p.eps_ref,
+                     lat->p.n_ref, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 16;
+  hipLaunchKernelGGL(copy_kernel, dim3(4096), dim3(256), 0, s,
+                     (const f32x4*)src, (f32x4*)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace rlb

@@ -1,0 +1,285 @@
+"""ctypes binding of librlb (C ABI in include/rlb.h).
+
+Argument marshalling only: every computation runs in the HIP kernels of
+librlb.so.  PyTorch supplies device memory (the workspace and I/O tensors)
+and the stream.  If the library is not built, every entry point raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librlb.so")
+
+OK, EINVAL, EDEVICE, ENOMEM, ENONFINITE, ELANDAU, ESTATE, EUNSUPPORTED = range(8)
+STATUS_NAMES = ["RLB_OK", "RLB_EINVAL", "RLB_EDEVICE", "RLB_ENOMEM", "RLB_ENONFINITE",
+                "RLB_ELANDAU", "RLB_ESTATE", "RLB_EUNSUPPORTED"]
+WALLS_Y = 0x1
+FULL26 = 0x2
+FIELDS = ["eps", "beta_x", "beta_y", "n", "T00", "T0x", "T0y", "Txx", "Txy", "Tyy",
+          "J0", "Jx", "Jy"]
+
+# Every symbol include/rlb.h declares.
+SYMBOLS = [
+    "rlb_workspace_bytes", "rlb_create", "rlb_destroy", "rlb_init_fields",
+    "rlb_set_obstacles", "rlb_add_disks", "rlb_clear_obstacles", "rlb_set_body_force",
+    "rlb_set_stirring", "rlb_step", "rlb_read_fields", "rlb_conserved", "rlb_sync",
+    "rlb_get_step", "rlb_state_bytes", "rlb_save_state", "rlb_load_state", "rlb_layout",
+    "rlb_stirring_coefficients", "rlb_stirring_field", "rlb_philox", "rlb_timing",
+    "rlb_timing_read", "rlb_copy_probe", "rlb_last_error", "rlb_version",
+]
+
+
+class RLBError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {message}")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("eps_ref", ctypes.c_double), ("n_ref", ctypes.c_double)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32, _i64, _u32, _u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+_sz, _d = ctypes.c_size_t, ctypes.c_double
+_P = ctypes.POINTER
+
+
+def lib():
+    """Load librlb.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2205_04658_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "rlb_workspace_bytes": [_P(Params), _P(_sz)],
+        "rlb_create": [_P(Params), _vp, _sz, _vp, _P(_vp)],
+        "rlb_destroy": [_vp],
+        "rlb_init_fields": [_vp, _vp, _vp, _vp, _vp],
+        "rlb_set_obstacles": [_vp, _vp],
+        "rlb_add_disks": [_vp, _i32, _vp],
+        "rlb_clear_obstacles": [_vp],
+        "rlb_set_body_force": [_vp, _d, _d],
+        "rlb_set_stirring": [_vp, _d, _d, _d, _u64],
+        "rlb_step": [_vp, _i64],
+        "rlb_read_fields": [_vp, _u32, _vp],
+        "rlb_conserved": [_vp, _P(_d)],
+        "rlb_sync": [_vp],
+        "rlb_get_step": [_vp, _P(_i64)],
+        "rlb_state_bytes": [_vp, _P(_sz)],
+        "rlb_save_state": [_vp, _vp, _sz],
+        "rlb_load_state": [_vp, _vp, _sz],
+        "rlb_layout": [_vp, _P(_i32), _P(_i64), _P(_sz)],
+        "rlb_stirring_coefficients": [_vp, _i64, _vp, _P(_i32)],
+        "rlb_stirring_field": [_vp, _i64, _vp],
+        "rlb_philox": [_u64, _u64, _u64, _i64, _vp, _vp],
+        "rlb_timing": [_vp, _i32],
+        "rlb_timing_read": [_vp, _P(_d), _P(_i64)],
+        "rlb_copy_probe": [_vp, _vp, _sz, _vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.rlb_last_error.restype = ctypes.c_char_p
+    L.rlb_last_error.argtypes = []
+    L.rlb_version.restype = ctypes.c_char_p
+    L.rlb_version.argtypes = []
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != OK:
+        raise RLBError(status, lib().rlb_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    return _vp(stream.cuda_stream if stream is not None else 0)
+
+
+def workspace_bytes(nx, ny, tau, cfl=1.0, flags=0, eps_ref=1.0, n_ref=0.1):
+    p = Params(nx, ny, tau, cfl, flags, eps_ref, n_ref)
+    n = _sz()
+    check(lib().rlb_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def philox(k0, k1, c1, count, device="cuda"):
+    """Raw Philox4x64-10 blocks from the device generator: (count, 4) uint64
+    (as int64 storage) for counters (m, c1, 0, 0), m < count."""
+    torch = _torch()
+    out = torch.empty((max(count, 1), 4), dtype=torch.int64, device=device)
+    check(lib().rlb_philox(k0, k1, c1, count, _vp(out.data_ptr()),
+                           _stream_ptr(torch.cuda.current_stream())))
+    return out[:count]
+
+
+def copy_probe(src, dst):
+    torch = _torch()
+    check(lib().rlb_copy_probe(_vp(src.data_ptr()), _vp(dst.data_ptr()),
+                               src.numel() * src.element_size(),
+                               _stream_ptr(torch.cuda.current_stream())))
+
+
+def _dev_f32(a, device, shape):
+    torch = _torch()
+    t = torch.as_tensor(np.asarray(a) if not isinstance(a, torch.Tensor) else a)
+    t = t.to(device=device, dtype=torch.float32).contiguous()
+    if tuple(t.shape) != shape:
+        raise ValueError(f"field has shape {tuple(t.shape)}, expected {shape}")
+    return t
+
+
+class Lattice:
+    """One lattice on one GPU.  The workspace is a torch uint8 tensor owned by
+    this object; all work goes to the torch stream current at creation."""
+
+    def __init__(self, nx, ny, tau, cfl=1.0, walls=False, full26=False,
+                 eps_ref=1.0, n_ref=0.1, device=None):
+        torch = _torch()
+        self.nx, self.ny = int(nx), int(ny)
+        flags = (WALLS_Y if walls else 0) | (FULL26 if full26 else 0)
+        self.params = Params(self.nx, self.ny, float(tau), float(cfl), flags,
+                             float(eps_ref), float(n_ref))
+        n = _sz()
+        check(lib().rlb_workspace_bytes(ctypes.byref(self.params), ctypes.byref(n)))
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _vp()
+        check(lib().rlb_create(ctypes.byref(self.params), _vp(self.workspace.data_ptr()), n.value,
+                               _stream_ptr(self.stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rlb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup --------------------------------------------------------------
+    def init_fields(self, eps, bx, by, n):
+        shape = (self.ny, self.nx)
+        ts = [_dev_f32(a, self.device, shape) for a in (eps, bx, by, n)]
+        check(lib().rlb_init_fields(self._h, *[_vp(t.data_ptr()) for t in ts]))
+        self._keep = ts
+
+    def set_obstacles(self, mask):
+        torch = _torch()
+        m = torch.as_tensor(np.asarray(mask) if not isinstance(mask, torch.Tensor) else mask)
+        m = m.to(device=self.device, dtype=torch.uint8).contiguous()
+        check(lib().rlb_set_obstacles(self._h, _vp(m.data_ptr())))
+        self._keep = [m]
+
+    def add_disks(self, discs):
+        d = np.ascontiguousarray(np.asarray(discs, np.float64).reshape(-1, 3))
+        check(lib().rlb_add_disks(self._h, d.shape[0], d.ctypes.data_as(_vp)))
+
+    def clear_obstacles(self):
+        check(lib().rlb_clear_obstacles(self._h))
+
+    def set_body_force(self, fx, fy=0.0):
+        check(lib().rlb_set_body_force(self._h, float(fx), float(fy)))
+
+    def set_stirring(self, kmin, kmax, amplitude, seed):
+        check(lib().rlb_set_stirring(self._h, float(kmin), float(kmax), float(amplitude), int(seed)))
+
+    # -- stepping -----------------------------------------------------------
+    def step(self, n=1):
+        check(lib().rlb_step(self._h, int(n)))
+
+    def sync(self):
+        check(lib().rlb_sync(self._h))
+
+    @property
+    def step_count(self):
+        s = _i64()
+        check(lib().rlb_get_step(self._h, ctypes.byref(s)))
+        return s.value
+
+    # -- read-out -----------------------------------------------------------
+    def fields(self, names=None):
+        """Dict name -> float32 tensor (ny, nx) of the current fields."""
+        torch = _torch()
+        names = FIELDS if names is None else list(names)
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELDS.index(nm)
+        order = [f for f in FIELDS if mask & (1 << FIELDS.index(f))]
+        out = torch.empty((len(order), self.ny, self.nx), dtype=torch.float32, device=self.device)
+        check(lib().rlb_read_fields(self._h, mask, _vp(out.data_ptr())))
+        return {nm: out[i] for i, nm in enumerate(order)}
+
+    def conserved(self):
+        out = (_d * 4)()
+        check(lib().rlb_conserved(self._h, out))
+        return np.array(out[:])
+
+    def layout(self):
+        q, pitch, hb = _i32(), _i64(), _sz()
+        check(lib().rlb_layout(self._h, ctypes.byref(q), ctypes.byref(pitch), ctypes.byref(hb)))
+        return q.value, pitch.value, hb.value
+
+    def save_state(self):
+        torch = _torch()
+        n = _sz()
+        check(lib().rlb_state_bytes(self._h, ctypes.byref(n)))
+        buf = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        check(lib().rlb_save_state(self._h, _vp(buf.data_ptr()), n.value))
+        return buf
+
+    def load_state(self, buf):
+        check(lib().rlb_load_state(self._h, _vp(buf.data_ptr()), buf.numel()))
+
+    def planes(self, buf=None):
+        """Shifted population planes of a saved state: (F, G) float32 tensors
+        of shape (Q, ny, nx) holding F_i - w_i eps_ref and G_i - w_i n_ref."""
+        torch = _torch()
+        buf = self.save_state() if buf is None else buf
+        q, pitch, hb = self.layout()
+        f = buf[hb:].view(torch.float32).view(2 * q, pitch)[:, :self.nx * self.ny]
+        f = f.reshape(2 * q, self.ny, self.nx)
+        return f[:q], f[q:]
+
+    def stirring_coefficients(self, step):
+        torch = _torch()
+        out = torch.empty((8192, 4), dtype=torch.float64, device=self.device)
+        cnt = _i32()
+        check(lib().rlb_stirring_coefficients(self._h, int(step), _vp(out.data_ptr()),
+                                              ctypes.byref(cnt)))
+        return out[:cnt.value]
+
+    def stirring_field(self, step):
+        torch = _torch()
+        out = torch.empty((2, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        check(lib().rlb_stirring_field(self._h, int(step), _vp(out.data_ptr())))
+        return out
+
+    def timing(self, enable=True):
+        check(lib().rlb_timing(self._h, 1 if enable else 0))
+
+    def timing_read(self):
+        ms, n = _d(), _i64()
+        check(lib().rlb_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,178 @@
+"""GPU parity of the fused RLB step against the FP64 oracle (through the C
+ABI via the ctypes binding)."""
+import numpy as np
+import pytest
+
+from oracle import forcing, geometry, rlb
+from paper_2205_04658_amd import workloads
+from rlbtest import compare, fold, need_gpu, oracle_run, scales, unfold26
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def make_lattice(f, tau, **kw):
+    from paper_2205_04658_amd.rlb import Lattice
+    ny, nx = f["eps"].shape
+    lat = Lattice(nx, ny, tau, **kw)
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    return lat
+
+
+def test_philox_bit_exact():
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import philox
+    for k0, k1, c1 in [(0, 0, 0), (2205, 0, 17), (2**63 + 5, 2**40 + 3, 2**33 + 1)]:
+        got = philox(k0, k1, c1, 300).cpu().numpy().view(np.uint64)
+        for m in range(300):
+            want = forcing.philox4x64_10((m, c1, 0, 0), (k0, k1))
+            assert tuple(int(v) for v in got[m]) == want, (k0, k1, c1, m)
+
+
+@pytest.mark.parametrize("shell", [(7, 9, 1e-5, 2205), (31, 33, 5e-6, 4658), (0.5, 3.2, 1e-3, 1)])
+def test_stirring_coefficients_and_field(shell):
+    torch = need_gpu()
+    nx, ny = 96, 80
+    lat = make_lattice(workloads.uniform(nx, ny), 0.8)
+    kmin, kmax, amp, seed = shell
+    if kmax >= min(nx, ny) / 2:
+        nx = ny = 128
+        lat = make_lattice(workloads.uniform(nx, ny), 0.8)
+    lat.set_stirring(kmin, kmax, amp, seed)
+    modes = forcing.shell_modes(kmin, kmax)
+    for step in (0, 7, 123456):
+        c = lat.stirring_coefficients(step).cpu().numpy()
+        cx, cy = forcing.stirring_coefficients(modes, seed, step, amp)
+        want = np.stack([cx.real, cx.imag, cy.real, cy.imag], 1)
+        assert c.shape == want.shape
+        np.testing.assert_allclose(c, want, rtol=1e-13, atol=1e-13 * amp)
+        fld = lat.stirring_field(step).double().cpu().numpy()
+        ref = forcing.synthesize(modes, cx, cy, nx, ny)
+        rms = np.sqrt((ref ** 2).mean())
+        assert np.abs(fld - ref).max() < 2e-5 * rms
+
+
+def test_init_fields_match():
+    torch = need_gpu()
+    f = workloads.random_fields(67, 37, seed=3)
+    for full in (False, True):
+        lat = make_lattice(f, 0.7, full26=full)
+        F, G = oracle_run(f, 0, 0.7)
+        err = compare(lat.fields(), rlb.fields(F, G), scales(beta=0.05))
+        assert max(err.values()) < TOL, err
+        # populations themselves: folded / full planes vs oracle
+        pf, pg = lat.planes()
+        w = rlb.W[:, None, None]
+        want_f = (unfold26 if full else fold)(F - w * 1.0)
+        want_g = (unfold26 if full else fold)(G - w * 0.1)
+        assert np.abs(pf.double().cpu().numpy() - want_f).max() < 1e-8
+        assert np.abs(pg.double().cpu().numpy() - want_g).max() < 1e-9
+
+
+CASES = {
+    "periodic": dict(),
+    "cfl_half": dict(cfl=0.5),
+    "body_force": dict(body=(2e-4, -1e-4)),
+    "stirring": dict(stir=(2.0, 4.5, 2e-4, 11)),
+    "walls_discs": dict(walls=True, discs=[(20.5, 17.0, 6.0), (60.2, 25.7, 4.0)], body=(1e-4, 0.0)),
+    "cfl_half_walls": dict(cfl=0.5, walls=True, discs=[(5.0, 5.0, 3.0)], stir=(1.0, 3.0, 1e-4, 5)),
+}
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_step_parity(case, full):
+    """67 x 37 lattice (ragged tiles in x and y), 40 steps."""
+    torch = need_gpu()
+    c = CASES[case]
+    nx, ny, tau, steps = 67, 37, 0.7, 40
+    f = workloads.random_fields(nx, ny, seed=5)
+    cfl = c.get("cfl", 1.0)
+    solid = None
+    lat = make_lattice(f, tau, cfl=cfl, full26=full, walls=c.get("walls", False))
+    if c.get("walls") or c.get("discs"):
+        solid = geometry.disc_mask(nx, ny, c.get("discs", []))
+        if c.get("walls"):
+            solid[0] = solid[-1] = True
+        lat.add_disks(np.array(c.get("discs", []), np.float64).reshape(-1, 3))
+    body = c.get("body", (0.0, 0.0))
+    lat.set_body_force(*body)
+    stir = c.get("stir")
+    if stir:
+        lat.set_stirring(*stir)
+    lat.step(steps)
+    lat.sync()
+    F, G = oracle_run(f, steps, tau, cfl=cfl, solid=solid, body=body, stir=stir)
+    g = lat.fields()
+    o = rlb.fields(F, G, cfl=cfl, solid=solid)
+    err = compare(g, o, scales(beta=0.05))
+    assert max(err.values()) < TOL, err
+    if solid is not None:   # the rasterised mask matches bit for bit
+        np.testing.assert_array_equal(g["eps"].cpu().numpy() == 0.0, solid)
+    tot = lat.conserved()
+    want = rlb.totals(F, G)
+    assert abs(tot[0] - want[0]) < 1e-6 * want[0]
+    assert abs(tot[3] - want[3]) < 1e-6 * want[3]
+    assert np.abs(tot[1:3] - want[1:3]).max() < 1e-6 * want[0]
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
+def test_shear_wave_1000_steps(full):
+    """Shear-wave workload: 64 x 64, tau = 0.8, 1000 steps; every field
+    within 1e-5 of its scale."""
+    torch = need_gpu()
+    cfg = workloads.SHEAR
+    f = workloads.shear_wave(cfg["nx"], cfg["ny"], cfg["amp"])
+    lat = make_lattice(f, cfg["tau"], full26=full)
+    lat.step(cfg["steps"])
+    lat.sync()
+    F, G = oracle_run(f, cfg["steps"], cfg["tau"])
+    err = compare(lat.fields(), rlb.fields(F, G), scales(beta=cfg["amp"]))
+    assert max(err.values()) < TOL, err
+
+
+def test_conservation_drift():
+    torch = need_gpu()
+    f = workloads.random_fields(128, 96, seed=8)
+    lat = make_lattice(f, 0.6)
+    t0 = lat.conserved()
+    lat.step(1000)
+    t1 = lat.conserved()
+    # float32 populations: the drift is rounding only (no systematic bias)
+    E = t0[0]
+    assert abs(t1[0] - t0[0]) < 2e-9 * E, (t1 - t0) / E
+    assert np.abs(t1[1:3] - t0[1:3]).max() < 2e-9 * E, (t1 - t0) / E
+    assert abs(t1[3] - t0[3]) < 2e-9 * t0[3], (t1 - t0) / t0[3]
+
+
+def test_determinism_and_resume():
+    torch = need_gpu()
+    f = workloads.random_fields(80, 72, seed=9)
+    runs = []
+    for _ in range(2):
+        lat = make_lattice(f, 0.6)
+        lat.set_stirring(2, 5, 1e-4, 3)
+        lat.step(30)
+        runs.append(lat.save_state().cpu())
+    assert torch.equal(runs[0], runs[1])
+    lat = make_lattice(f, 0.6)
+    lat.set_stirring(2, 5, 1e-4, 3)
+    lat.step(15)
+    snap = lat.save_state()
+    lat2 = make_lattice(workloads.uniform(80, 72), 0.6)
+    lat2.set_stirring(2, 5, 1e-4, 3)
+    lat2.load_state(snap)
+    assert lat2.step_count == 15
+    lat2.step(15)
+    assert torch.equal(lat2.save_state().cpu(), runs[0])
+
+
+def test_landau_failure_is_reported():
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import RLBError, ELANDAU
+    f = workloads.uniform(16, 16)
+    f["bx"][3, 4] = 1.5           # superluminal initial velocity
+    lat = make_lattice(f, 0.7)
+    with pytest.raises(RLBError) as e:
+        lat.sync()
+    assert e.value.status == ELANDAU
