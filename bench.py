@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % HBM peak, 4096² forced RLB; batched/adjoint vs plain, same GPU"
 KERNEL_SOURCES = ["paper_2205_04658_amd/csrc/step.hip", "paper_2205_04658_amd/csrc/device_common.hpp",
+                  "paper_2205_04658_amd/csrc/forcing.hip",
                   "paper_2205_04658_amd/csrc/dirset.hpp", "paper_2205_04658_amd/csrc/internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_forced4096_traffic.json")
 
@@ -113,6 +114,8 @@ def run_plain(torch, rlb, workloads, layout, steps, warmup):
     f = workloads.uniform(nx, ny, c["eps"], c["n"])
     lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
     lat.set_stirring(c["kmin"], c["kmax"], c["amplitude"], c["seed"])
+    lat.step(2)
+    tune = lat.autotune(trials=5)          # keeps the fastest launch shape
     lat.step(warmup)
     lat.sync()
     lat.timing(True)
@@ -126,15 +129,59 @@ def run_plain(torch, rlb, workloads, layout, steps, warmup):
     lat.sync()
     q = lat.layout()[0]
     cells = nx * ny
-    K = 33
-    bytes_per_launch = 2 * 2 * q * 4 * cells + ny * (K + 1) * 16
+    # algorithmic bytes of one step-kernel launch: every population plane
+    # read once and written once (2 families x q planes x 4 B each way)
+    # plus the two float32 stirring-force planes read
+    bytes_per_cell = 2 * 2 * q * 4 + 2 * 4
+    bytes_per_launch = bytes_per_cell * cells
     kernel_ms = kms / max(launches, 1)
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     out = dict(layout=layout, planes=q, mlups=cells * steps / wall / 1e6, ms_per_step=wall / steps * 1e3,
-               kernel_ms=kernel_ms, kernel_launches=launches, bytes_per_cell=16 * q,
+               kernel_ms=kernel_ms, kernel_launches=launches, bytes_per_cell=bytes_per_cell,
                bytes_per_launch=bytes_per_launch, achieved_gbs=achieved,
-               traffic=measured_traffic(layout))
+               traffic=measured_traffic(layout), shape=lat.launch_shape(),
+               tune=[list(r) for r in tune])
     del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_batch(torch, rlb, workloads, steps, warmup):
+    """The batched channel workload: 64 lattices W ~ U{256..2048} x
+    H ~ U{128..512}, bounce-back walls, discs of radius 6 at 1/5/10 % area,
+    body force 1e-6 along x, tau 0.8, one launch per step over all lattices,
+    replayed from a hipGraph."""
+    c = workloads.CHANNELS
+    lats = workloads.channel_batch(c["count"], c["seed"], c["wmin"], c["wmax"], c["hmin"],
+                                   c["hmax"], c["radius"], c["fractions"])
+    B = rlb.Batch([(d["nx"], d["ny"]) for d in lats], c["tau"], walls=True,
+                  eps_ref=c["eps"], n_ref=c["n"])
+    for b, d in enumerate(lats):
+        f = workloads.uniform(d["nx"], d["ny"], c["eps"], c["n"])
+        B[b].init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        B[b].add_disks(d["discs"])
+    B.set_body_force(c["body_force"], 0.0)
+    B.step(2)
+    tune = B.autotune(trials=3)
+    B.step(warmup)
+    B.sync()
+    cells = B.info()["cells"]
+    B.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gms, gsteps = B.timing_read()
+    B.sync()
+    q = B.info()["planes"]
+    out = dict(count=len(lats), cells=cells, steps=steps, mlups=cells * steps / wall / 1e6,
+               ms_per_step=wall / steps * 1e3, gpu_ms_per_step=gms / max(gsteps, 1),
+               bytes_per_cell=2 * 2 * q * 4 + 1, shape=B.launch_shape(),
+               tune=[list(r) for r in tune])
+    out["achieved_gbs"] = out["bytes_per_cell"] * cells / (out["gpu_ms_per_step"] * 1e-3) / 1e9
+    B.close()
+    del B
     torch.cuda.empty_cache()
     return out
 
@@ -147,6 +194,7 @@ def main():
     ap.add_argument("--layout", default="folded17", choices=["folded17", "full26"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -163,6 +211,10 @@ def main():
         variants[other] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms", "bytes_per_cell",
                                              "achieved_gbs")}
         variants[other]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
+    batched = None
+    if not a.no_batch:
+        batched = run_batch(torch, rlb, workloads, max(a.steps // 5, 50), 20)
+        batched["vs_plain"] = batched["mlups"] / main_run["mlups"]
     copy_gbs = copy_probe_gbs(torch, rlb)
     cpu = None if a.no_cpu_baseline else cpu_baseline()
     r = main_run
@@ -174,6 +226,7 @@ def main():
         "config": {"workload": "forced turbulence 4096x4096 periodic, tau 0.52, stirring "
                                "31<=|k|<=33 (412 modes), amplitude 5e-6, seed 4658",
                    "layout": r["layout"], "planes_per_family": r["planes"],
+                   "launch_shape": {"tile_rows": r["shape"][0], "grid_per_cu": r["shape"][1]},
                    "precision": "f32 populations (shifted), f64 Landau solve and reductions",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS,
@@ -181,6 +234,7 @@ def main():
                      "traffic": r["traffic"], "kernel_ms": r["kernel_ms"],
                      "bytes_per_cell": r["bytes_per_cell"], "bytes_per_launch": r["bytes_per_launch"]},
         "copy_probe_gbs": copy_gbs,
+        "batched": batched,
         "variants": variants,
         "cpu_baseline": cpu,
     }

@@ -204,6 +204,81 @@ rlb_status rlb_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count,
 rlb_status rlb_timing(rlb_lattice* lat, int32_t enable);
 rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches);
 
+/* Launch shape of the step kernel: tiles of 64 x tile_rows nodes (one
+ * wavefront per row; tile_rows in {1, 2, 4, 8}, other than 4 only for the
+ * folded layout) and the grid: grid_per_cu = 0 launches one workgroup per
+ * tile, k > 0 launches about k resident workgroups of 4 wavefronts per CU
+ * that walk the tile list.  Results do not depend on the shape (bitwise). */
+rlb_status rlb_set_launch_shape(rlb_lattice* lat, int32_t tile_rows, int32_t grid_per_cu);
+rlb_status rlb_get_launch_shape(const rlb_lattice* lat, int32_t* tile_rows, int32_t* grid_per_cu);
+
+/* Autotuner: time `trials` step-kernel launches for every candidate shape
+ * (tile_rows x grid_per_cu in {0, 2, 4, 8}) on the current state -- each
+ * launch reads the current copy and overwrites the other, so the state does
+ * not advance -- and keep the fastest.  If h_ms is not null, up to
+ * max_results rows (tile_rows, grid_per_cu, ms per launch) are written.
+ * Synchronises. */
+rlb_status rlb_autotune(rlb_lattice* lat, int32_t trials, double* h_ms, int32_t max_results);
+
+/* ------------------------------------------------------------------------
+ * Batched lattices: many lattices of uneven sizes that share tau, cfl,
+ * flags and references advance together, one launch per step over the
+ * concatenated tile lists of all members (a persistent or one-workgroup-
+ * per-tile grid), replayed from a captured hipGraph.  Each member evolves
+ * bitwise as the same lattice stepped alone.
+ * ------------------------------------------------------------------------ */
+typedef struct rlb_batch rlb_batch;   /* opaque, host heap */
+
+/* Workspace bytes for `count` members of sizes h_nx[b] x h_ny[b] (host
+ * arrays); p supplies tau, cfl, flags, eps_ref, n_ref (p->nx, p->ny are
+ * ignored). */
+rlb_status rlb_batch_workspace_bytes(const rlb_params* p, int32_t count,
+                                     const int32_t* h_nx, const int32_t* h_ny,
+                                     size_t* bytes);
+
+/* Create the batch and its members inside d_workspace.  Graph replay needs a
+ * non-null stream; with the null stream every step is a direct launch. */
+rlb_status rlb_batch_create(const rlb_params* p, int32_t count,
+                            const int32_t* h_nx, const int32_t* h_ny,
+                            void* d_workspace, size_t bytes, void* hip_stream,
+                            rlb_batch** out);
+rlb_status rlb_batch_destroy(rlb_batch* batch);
+
+/* Handle of member b for every single-lattice call except stepping and
+ * forcing (rlb_init_fields, rlb_add_disks, rlb_set_obstacles,
+ * rlb_read_fields, rlb_conserved, rlb_save_state, ...).  rlb_step on a
+ * member returns RLB_EINVAL.  The handle is owned by the batch. */
+rlb_status rlb_batch_member(rlb_batch* batch, int32_t b, rlb_lattice** out);
+
+/* Uniform body force of every member (Ch. 4 eq. forceTerm). */
+rlb_status rlb_batch_set_body_force(rlb_batch* batch, double fx, double fy);
+
+/* Advance every member nsteps steps.  All members must be at the same
+ * ping-pong phase (they are unless a member was re-initialised alone):
+ * otherwise RLB_ESTATE. */
+rlb_status rlb_batch_step(rlb_batch* batch, int64_t nsteps);
+
+/* Wait for queued work; report device failures of batched steps. */
+rlb_status rlb_batch_sync(rlb_batch* batch);
+
+/* Members, total nodes, planes per family and steps taken. */
+rlb_status rlb_batch_info(const rlb_batch* batch, int32_t* count, int64_t* cells,
+                          int32_t* planes, int64_t* step);
+
+/* Launch shape (as rlb_set_launch_shape) and autotuner (as rlb_autotune)
+ * of the batched step; graph replay of steps_per_graph (even, 0 = off,
+ * default 16) steps per launch. */
+rlb_status rlb_batch_set_launch_shape(rlb_batch* batch, int32_t tile_rows, int32_t grid_per_cu);
+rlb_status rlb_batch_get_launch_shape(const rlb_batch* batch, int32_t* tile_rows,
+                                      int32_t* grid_per_cu);
+rlb_status rlb_batch_autotune(rlb_batch* batch, int32_t trials, double* h_ms, int32_t max_results);
+rlb_status rlb_batch_use_graph(rlb_batch* batch, int32_t steps_per_graph);
+
+/* Wall time of rlb_batch_step calls between HIP events on the batch stream
+ * (each call synchronises while timing is on). */
+rlb_status rlb_batch_timing(rlb_batch* batch, int32_t enable);
+rlb_status rlb_batch_timing_read(rlb_batch* batch, double* total_ms, int64_t* steps);
+
 /* A plain device copy of `bytes` (multiple of 16) for bandwidth calibration. */
 rlb_status rlb_copy_probe(const void* d_src, void* d_dst, size_t bytes,
                           void* hip_stream);

@@ -79,7 +79,10 @@ Workspace layout(const rlb_params* p, int Q, int64_t pitch) {
   w.modes_off = off; off += align_up((size_t)kMaxModes * sizeof(int4));
   w.bins_off = off; off += align_up((size_t)(kMaxK + 2) * sizeof(int32_t));
   w.table_off = off; off += align_up((size_t)p->ny * (kMaxK + 1) * sizeof(float4));
+  w.phase_off = off; off += align_up((size_t)p->ny * sizeof(double2));
+  w.force_off = off; off += align_up((size_t)2 * pitch * sizeof(float));
   w.partial_off = off; off += align_up((size_t)kRedBlocks * 4 * sizeof(double));
+  w.desc_off = off; off += align_up(sizeof(LatDesc));
   w.misc_off = off; off += align_up(256);
   w.total = off;
   return w;
@@ -118,6 +121,9 @@ StirArgs stir_args(const rlb_lattice* lat) {
   a.bins = lat->bins;
   a.coef = lat->coef;
   a.table = lat->table;
+  a.phase = lat->phase;
+  a.force = lat->force;
+  a.force_pitch = lat->pitch;
   a.dstep = lat->dstep;
   a.nmodes = lat->nmodes;
   a.K = lat->K;
@@ -159,6 +165,8 @@ rlb_status accumulate_timing(rlb_lattice* lat) {
 }
 
 }  // namespace
+
+void rlb::set_error_message(const char* msg) { g_err = msg; }
 
 extern "C" {
 
@@ -219,9 +227,24 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   lat->modes = (int4*)(lat->ws + w.modes_off);
   lat->bins = (int32_t*)(lat->ws + w.bins_off);
   lat->table = (float4*)(lat->ws + w.table_off);
+  lat->phase = (double2*)(lat->ws + w.phase_off);
+  lat->force = (float*)(lat->ws + w.force_off);
   lat->partials = (double*)(lat->ws + w.partial_off);
   lat->err = (uint32_t*)(lat->ws + w.misc_off);
   lat->dstep = (int64_t*)(lat->ws + w.misc_off + 64);
+  lat->d_desc = (LatDesc*)(lat->ws + w.desc_off);
+  lat->num_cu = prop.multiProcessorCount;
+  lat->shape.tile_rows = 4;
+  lat->shape.grid_per_cu = 0;
+  lat->desc.state[0] = lat->state[0];
+  lat->desc.state[1] = lat->state[1];
+  lat->desc.mask = lat->mask;
+  lat->desc.force = (const float*)(lat->ws + w.force_off);
+  lat->desc.pitch = pitch;
+  lat->desc.nx = p->nx;
+  lat->desc.ny = p->ny;
+  lat->desc.tiles_x = (p->nx + 63) / 64;
+  lat->desc.tile_begin = 0;
   lat->result = (double*)(lat->ws + w.misc_off + 128);
   if (Q == 17) fill_taps<Dir17>(lat); else fill_taps<Dir26>(lat);
 
@@ -229,6 +252,9 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   e = launch_fill_u8(lat->mask, (size_t)p->nx * p->ny, 0, lat->stream);
   if (e == hipSuccess) e = launch_fill_u8((uint8_t*)lat->err, 64, 0, lat->stream);
   if (e == hipSuccess) e = launch_set_i64(lat->dstep, 0, lat->stream);
+  if (e == hipSuccess) e = launch_phase(lat);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(lat->d_desc, &lat->desc, sizeof(LatDesc), hipMemcpyHostToDevice, lat->stream);
   if (e == hipSuccess && (p->flags & RLB_WALLS_Y)) {
     e = launch_walls(lat);
     lat->any_solid = true;
@@ -372,12 +398,14 @@ rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax, double a
 rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps) {
   if (rlb_status s = check_lat(lat)) return s;
   if (nsteps < 0) return fail(RLB_EINVAL, "nsteps must be >= 0");
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: step it with rlb_batch_step");
   const int force = lat->stir ? FORCE_STIR : ((lat->fx != 0.0 || lat->fy != 0.0) ? FORCE_BODY : FORCE_NONE);
   const StirArgs sa = stir_args(lat);
   for (int64_t t = 0; t < nsteps; ++t) {
     if (lat->stir) {
       HIP_TRY(launch_stir_draw(sa, -1, lat->stream), "stirring draw");
       HIP_TRY(launch_stir_table(sa, lat->stream), "stirring table");
+      HIP_TRY(launch_stir_synth(sa, lat->stream), "stirring synthesis");
     }
     int slot = 0;
     if (lat->timing) {
@@ -385,8 +413,7 @@ rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps) {
       if (rlb_status s = drain_event(lat, slot)) return s;
       HIP_TRY(hipEventRecord(lat->ev[slot][0], lat->stream), "event record");
     }
-    HIP_TRY(launch_step(lat, MODE_STEP, force, lat->state[lat->cur], lat->state[lat->cur ^ 1],
-                        nullptr, 0), "step kernel");
+    HIP_TRY(launch_step(lat, MODE_STEP, force, lat->cur, nullptr, 0), "step kernel");
     if (lat->timing) {
       HIP_TRY(hipEventRecord(lat->ev[slot][1], lat->stream), "event record");
       lat->ev_pending |= 1u << slot;
@@ -402,8 +429,7 @@ rlb_status rlb_read_fields(rlb_lattice* lat, uint32_t field_mask, float* d_out) 
   if (field_mask == 0 || field_mask >= (1u << RLB_FIELD_COUNT))
     return fail(RLB_EINVAL, "field_mask must select fields 0..%d", RLB_FIELD_COUNT - 1);
   if (!d_out || !aligned(d_out, 4)) return fail(RLB_EINVAL, "output must be a 4-byte aligned device pointer");
-  HIP_TRY(launch_step(lat, MODE_FIELDS, FORCE_NONE, lat->state[lat->cur], nullptr, d_out, field_mask),
-          "fields kernel");
+  HIP_TRY(launch_step(lat, MODE_FIELDS, FORCE_NONE, lat->cur, d_out, field_mask), "fields kernel");
   return RLB_OK;
 }
 
@@ -518,7 +544,11 @@ rlb_status rlb_stirring_field(rlb_lattice* lat, int64_t step, float* d_out) {
   const StirArgs a = stir_args(lat);
   HIP_TRY(launch_stir_draw(a, step, lat->stream), "stirring draw");
   HIP_TRY(launch_stir_table(a, lat->stream), "stirring table");
-  HIP_TRY(launch_stir_field(lat, d_out), "stirring field");
+  HIP_TRY(launch_stir_synth(a, lat->stream), "stirring synthesis");
+  const size_t plane = (size_t)lat->p.nx * lat->p.ny;
+  for (int c = 0; c < 2; ++c)
+    HIP_TRY(hipMemcpyAsync(d_out + c * plane, lat->force + c * lat->pitch, plane * sizeof(float),
+                           hipMemcpyDeviceToDevice, lat->stream), "copy force");
   return RLB_OK;
 }
 
@@ -553,6 +583,75 @@ rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches
   if (rlb_status s = accumulate_timing(lat)) return s;
   if (total_ms) *total_ms = lat->timed_ms;
   if (launches) *launches = lat->timed_launches;
+  return RLB_OK;
+}
+
+rlb_status rlb_set_launch_shape(rlb_lattice* lat, int32_t tile_rows, int32_t grid_per_cu) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!(tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8))
+    return fail(RLB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
+  if (grid_per_cu < 0 || grid_per_cu > 64) return fail(RLB_EINVAL, "grid_per_cu must be in [0, 64]");
+  lat->shape.tile_rows = tile_rows;
+  lat->shape.grid_per_cu = grid_per_cu;
+  return RLB_OK;
+}
+
+rlb_status rlb_get_launch_shape(const rlb_lattice* lat, int32_t* tile_rows, int32_t* grid_per_cu) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (tile_rows) *tile_rows = lat->shape.tile_rows;
+  if (grid_per_cu) *grid_per_cu = lat->shape.grid_per_cu;
+  return RLB_OK;
+}
+
+rlb_status rlb_autotune(rlb_lattice* lat, int32_t trials, double* h_ms, int32_t max_results) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (trials < 1 || trials > 1000) return fail(RLB_EINVAL, "trials must be in [1, 1000]");
+  const int force = lat->stir ? FORCE_STIR : ((lat->fx != 0.0 || lat->fy != 0.0) ? FORCE_BODY : FORCE_NONE);
+  const LaunchShape best = lat->shape;
+  auto run = [&](int n) -> hipError_t {
+    for (int i = 0; i < n; ++i) {   // reads the current copy, writes the other: state unchanged
+      hipError_t e = launch_step(lat, MODE_STEP, force, lat->cur, nullptr, 0);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  std::vector<LaunchShape> cand;
+  for (int ty : {1, 2, 4, 8})
+    for (int g : {0, 2, 4, 8})
+      if (lat->Q == 17 || ty == 4) cand.push_back(LaunchShape{ty, g});
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "event");
+  HIP_TRY(hipEventCreate(&e1), "event");
+  double best_ms = 1e300;
+  LaunchShape win = best;
+  int k = 0;
+  for (const LaunchShape& c : cand) {
+    lat->shape = c;
+    hipError_t e = run(2);
+    if (e == hipSuccess) e = hipEventRecord(e0, lat->stream);
+    if (e == hipSuccess) e = run(trials);
+    if (e == hipSuccess) e = hipEventRecord(e1, lat->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      lat->shape = best;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return hip_fail(e, "autotune");
+    }
+    const double per = ms / trials;
+    if (h_ms && k < max_results) {
+      h_ms[3 * k] = c.tile_rows;
+      h_ms[3 * k + 1] = c.grid_per_cu;
+      h_ms[3 * k + 2] = per;
+    }
+    ++k;
+    if (per < best_ms) { best_ms = per; win = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  lat->shape = win;
   return RLB_OK;
 }
 

@@ -25,15 +25,36 @@ __device__ __forceinline__ void static_for(F&& f) {
 //
 // eps is the largest real root of the characteristic cubic of A = T g: the
 // timelike eigenvalue exceeds the spacelike ones, which are minus the
-// rest-frame pressures.  The root comes from the trigonometric form of the
-// depressed cubic and is polished by two Newton steps; u is the cross
-// product of two rows of (A - eps I) (the pair with the largest product),
-// normalised to u.u = 1, u^0 > 0.  Returns false when the cubic has no three
-// real roots or the eigenvector is not timelike.
+// rest-frame pressures.  Newton's method on the cubic starts from the energy
+// density of the ideal conformal fluid with the same T^{00} and T^{0i},
+// eps0 = sqrt(4 T00^2 - 3 |T^{0i}|^2) - T00, which differs from eps only by
+// the viscous stress; two steps reach float64 precision.  The result is
+// accepted when the last step was small and the deflated quadratic has no
+// root above it (chi'(eps) > 0 and 3 eps > trace); otherwise the root is
+// taken from the trigonometric form of the depressed cubic.  u is the cross
+// product of two rows of (A - eps I), normalised to u.u = 1, u^0 > 0.
+// Returns false when no timelike eigenvector exists.
 // ---------------------------------------------------------------------------
 struct Frame {
   double eps, u0, ux, uy;
 };
+
+__device__ __noinline__ double cubic_largest_root(double c2, double c1, double c0) {
+  const double s = c2 * (1.0 / 3.0);
+  const double p = c1 - c2 * s;
+  const double q = (-2.0 * s * s + c1) * s - c0;
+  if (!(p < 0.0)) return -1.0;
+  const double r = sqrt(-p * (1.0 / 3.0));
+  double arg = -q / (2.0 * r * r * r);
+  arg = fmin(1.0, fmax(-1.0, arg));
+  double lam = 2.0 * r * cos(acos(arg) * (1.0 / 3.0)) + s;
+  for (int it = 0; it < 2; ++it) {
+    const double f = ((lam - c2) * lam + c1) * lam - c0;
+    const double d = (3.0 * lam - 2.0 * c2) * lam + c1;
+    if (d != 0.0) lam -= f / d;
+  }
+  return lam;
+}
 
 __device__ __forceinline__ bool landau3(double T00, double T0x, double T0y,
                                         double Txx, double Txy, double Tyy,
@@ -42,50 +63,46 @@ __device__ __forceinline__ bool landau3(double T00, double T0x, double T0y,
   const double a10 = T0x, a11 = -Txx, a12 = -Txy;
   const double a20 = T0y, a21 = -Txy, a22 = -Tyy;
   const double c2 = a00 + a11 + a22;
-  const double c1 = (a00 * a11 - a01 * a10) + (a00 * a22 - a02 * a20) +
-                    (a11 * a22 - a12 * a21);
-  const double c0 = a00 * (a11 * a22 - a12 * a21) -
-                    a01 * (a10 * a22 - a12 * a20) +
+  const double m12 = a11 * a22 - a12 * a21;
+  const double c1 = (a00 * a11 - a01 * a10) + (a00 * a22 - a02 * a20) + m12;
+  const double c0 = a00 * m12 - a01 * (a10 * a22 - a12 * a20) +
                     a02 * (a10 * a21 - a11 * a20);
-  // lambda^3 - c2 lambda^2 + c1 lambda - c0 = 0; lambda = t + s
-  const double s = c2 * (1.0 / 3.0);
-  const double p = c1 - c2 * s;
-  const double q = (-2.0 * s * s + c1) * s - c0;
-  if (!(p < 0.0)) return false;
-  const double r = sqrt(-p * (1.0 / 3.0));
-  double arg = -q / (2.0 * r * r * r);
-  arg = fmin(1.0, fmax(-1.0, arg));
-  double lam = 2.0 * r * cos(acos(arg) * (1.0 / 3.0)) + s;
+  const double disc = 4.0 * T00 * T00 - 3.0 * (T0x * T0x + T0y * T0y);
+  double lam = disc > 0.0 ? sqrt(disc) - T00 : T00;
+  double step = 0.0, d = 0.0;
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     const double f = ((lam - c2) * lam + c1) * lam - c0;
-    const double d = (3.0 * lam - 2.0 * c2) * lam + c1;
-    if (d != 0.0) lam -= f / d;
+    d = (3.0 * lam - 2.0 * c2) * lam + c1;
+    step = f / d;
+    lam -= step;
   }
+  if (!(fabs(step) <= 1e-10 * fabs(lam)) || !(d > 0.0) || !(3.0 * lam > c2))
+    lam = cubic_largest_root(c2, c1, c0);
+  if (!(lam > 0.0)) return false;
   // rows of (A - lam I)
   const double r0x = a00 - lam, r0y = a01, r0z = a02;
   const double r1x = a10, r1y = a11 - lam, r1z = a12;
   const double r2x = a20, r2y = a21, r2z = a22 - lam;
-  double vx = r1y * r2z - r1z * r2y;   // r1 x r2
+  double vx = r1y * r2z - r1z * r2y;   // r1 x r2: well conditioned for |beta| < ~0.6
   double vy = r1z * r2x - r1x * r2z;
   double vz = r1x * r2y - r1y * r2x;
   double nb = vx * vx + vy * vy + vz * vz;
-  {
+  double mn = vx * vx - vy * vy - vz * vz;
+  if (!(mn > 0.5 * nb)) {
     const double wx = r0y * r2z - r0z * r2y;   // r0 x r2
     const double wy = r0z * r2x - r0x * r2z;
     const double wz = r0x * r2y - r0y * r2x;
     const double nw = wx * wx + wy * wy + wz * wz;
     if (nw > nb) { vx = wx; vy = wy; vz = wz; nb = nw; }
+    const double ux = r0y * r1z - r0z * r1y;   // r0 x r1
+    const double uy = r0z * r1x - r0x * r1z;
+    const double uz = r0x * r1y - r0y * r1x;
+    const double nu = ux * ux + uy * uy + uz * uz;
+    if (nu > nb) { vx = ux; vy = uy; vz = uz; nb = nu; }
+    mn = vx * vx - vy * vy - vz * vz;
+    if (!(mn > 1e-12 * nb)) return false;
   }
-  {
-    const double wx = r0y * r1z - r0z * r1y;   // r0 x r1
-    const double wy = r0z * r1x - r0x * r1z;
-    const double wz = r0x * r1y - r0y * r1x;
-    const double nw = wx * wx + wy * wy + wz * wz;
-    if (nw > nb) { vx = wx; vy = wy; vz = wz; nb = nw; }
-  }
-  const double mn = vx * vx - vy * vy - vz * vz;
-  if (!(mn > 1e-12 * nb) || !(lam > 0.0)) return false;
   const double inv = (vx > 0.0 ? 1.0 : -1.0) / sqrt(mn);
   fr.eps = lam;
   fr.u0 = vx * inv;
@@ -108,15 +125,17 @@ struct EqCoef {
   float Ag, Bg;    // G_eq - w n_ref   = w (Ag + Bg s)
 };
 
+// kappa: see dirset.hpp (float32 quadrature correction of the s, s^2 terms).
 __device__ __forceinline__ EqCoef eq_coef(const Frame& fr, double n,
-                                          double eps_ref, double n_ref) {
+                                          double eps_ref, double n_ref,
+                                          double kappa) {
   EqCoef c;
   const double u2 = fr.ux * fr.ux + fr.uy * fr.uy;
   c.A = (float)((fr.eps - eps_ref) - 2.0 * fr.eps * u2);
-  c.B = (float)(4.0 * fr.eps * fr.u0);
-  c.C = (float)(10.0 * fr.eps);
+  c.B = (float)(4.0 * kappa * fr.eps * fr.u0);
+  c.C = (float)(10.0 * kappa * fr.eps);
   c.Ag = (float)(n * fr.u0 - n_ref);
-  c.Bg = (float)(3.0 * n);
+  c.Bg = (float)(3.0 * kappa * n);
   return c;
 }
 
@@ -133,41 +152,7 @@ __device__ __forceinline__ bool frame_from_beta(double eps, double bx,
   return true;
 }
 
-// ---------------------------------------------------------------------------
-// k-shell stirring force at column x of row y: the Hermitian shell sum
-// reduces, per row, to a real trigonometric series in th = 2 pi x / nx,
-//     F_c(x, y) = sum_{k=0..K} a_ck(y) cos(k th) + b_ck(y) sin(k th),
-// whose coefficients (a_x, b_x, a_y, b_y) per k are tabulated per row each
-// step.  cos/sin(k th) come from complex rotation by e^{i th}, re-anchored with an
-// exactly reduced sincospi every 8 harmonics to bound the rounding drift.
-// ---------------------------------------------------------------------------
-constexpr int kTableStride = 64;   // table entries per row (|k| <= 63)
-
-__device__ __forceinline__ void stir_series(const float4* __restrict__ table,
-                                            int K, float theta_scale, int nx,
-                                            int x, int y, float& fx, float& fy) {
-  const float4* __restrict__ row = table + (size_t)y * kTableStride;
-  float s1, c1;
-  sincospif((float)x * theta_scale, &s1, &c1);
-  float4 t = row[0];
-  float sx = t.x, sy = t.z;
-  float ck = 1.0f, sk = 0.0f;
-  for (int k = 1; k <= K; ++k) {
-    if ((k & 7) == 0) {
-      // re-anchor every 8 harmonics: k x reduced exactly modulo nx
-      sincospif((float)((k * x) % nx) * theta_scale, &sk, &ck);
-    } else {
-      const float cn = ck * c1 - sk * s1;
-      sk = sk * c1 + ck * s1;
-      ck = cn;
-    }
-    t = row[k];
-    sx += t.x * ck + t.y * sk;
-    sy += t.z * ck + t.w * sk;
-  }
-  fx += sx;
-  fy += sy;
-}
+constexpr int kTableStride = 64;   // stirring table entries per row (|k| <= 63)
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11) and the Box-Muller transform.

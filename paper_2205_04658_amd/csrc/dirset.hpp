@@ -21,6 +21,32 @@ constexpr double kWf = 1.0 / 21.0;
 constexpr double kWe = 4.0 / 105.0;
 constexpr double kWc = 9.0 / 280.0;
 
+// float32 weights for the shifted-storage arithmetic: multiples of 2^-28
+// within 5e-9 of 1/21, 4/105, 9/280 chosen so that 6 wf + 12 we + 8 wc = 1
+// exactly.  Float weights that do not sum to one would make the collision
+// leak energy systematically (sum_i w_i A != A for the equilibrium's
+// constant term).
+constexpr float kWf32 = 12782642.0f / 268435456.0f;
+constexpr float kWe32 = 10226113.0f / 268435456.0f;
+constexpr float kWc32 = 8628281.0f / 268435456.0f;
+static_assert(6.0 * 12782642 + 12.0 * 10226113 + 8.0 * 8628281 == 268435456.0,
+              "float weights must sum to one");
+
+// kappa = 1 / (3 sum_i w32_i vx_i^2) with the float32 weights and float32
+// direction components the kernels use.  The equilibrium's first- and
+// second-order coefficients are scaled by kappa so that, in the kernels'
+// own float32 arithmetic, the equilibrium carries exactly the momentum of
+// the Landau frame: otherwise the collision would change the momentum by
+// (kappa - 1) ~ 2.5e-8 of itself every step.
+constexpr double kappa_of(const float* w, const double* vx, int q) {
+  double s = 0.0;
+  for (int i = 0; i < q; ++i) {
+    const double v = (double)(float)vx[i];
+    s += (double)w[i] * v * v;
+  }
+  return 1.0 / (3.0 * s);
+}
+
 struct Dir17 {
   static constexpr int Q = 17;
   static constexpr double vx[Q] = {1, -1, 0, 0, kS2, -kS2, kS2, -kS2,
@@ -33,8 +59,12 @@ struct Dir17 {
   static constexpr double w[Q] = {kWf, kWf, kWf, kWf, kWe, kWe, kWe, kWe,
                                   2 * kWf, 2 * kWe, 2 * kWe, 2 * kWe, 2 * kWe,
                                   2 * kWc, 2 * kWc, 2 * kWc, 2 * kWc};
+  static constexpr float w32[Q] = {kWf32, kWf32, kWf32, kWf32, kWe32, kWe32, kWe32, kWe32,
+                                   2 * kWf32, 2 * kWe32, 2 * kWe32, 2 * kWe32, 2 * kWe32,
+                                   2 * kWc32, 2 * kWc32, 2 * kWc32, 2 * kWc32};
   static constexpr int opp[Q] = {1, 0, 3, 2, 7, 6, 5, 4,
                                  8, 10, 9, 12, 11, 16, 15, 14, 13};
+  static constexpr double kappa = kappa_of(w32, vx, Q);
 };
 
 struct Dir26 {
@@ -54,10 +84,14 @@ struct Dir26 {
   static constexpr double w[Q] = {kWf, kWf, kWf, kWf, kWe, kWe, kWe, kWe,
                                   kWf, kWe, kWe, kWe, kWe, kWc, kWc, kWc, kWc,
                                   kWf, kWe, kWe, kWe, kWe, kWc, kWc, kWc, kWc};
+  static constexpr float w32[Q] = {kWf32, kWf32, kWf32, kWf32, kWe32, kWe32, kWe32, kWe32,
+                                   kWf32, kWe32, kWe32, kWe32, kWe32, kWc32, kWc32, kWc32, kWc32,
+                                   kWf32, kWe32, kWe32, kWe32, kWe32, kWc32, kWc32, kWc32, kWc32};
   // opposite of (vx, vy, +vz) is (-vx, -vy, -vz): in the other vz group
   static constexpr int opp[Q] = {1, 0, 3, 2, 7, 6, 5, 4,
                                  17, 19, 18, 21, 20, 25, 24, 23, 22,
                                  8, 10, 9, 12, 11, 16, 15, 14, 13};
+  static constexpr double kappa = kappa_of(w32, vx, Q);
 };
 
 }  // namespace rlb

@@ -6,8 +6,11 @@
 // half-shell mode from Philox4x64-10 + Box-Muller in float64 (counter
 // (m, step, 0, 0), key (seed, stream)); (2) one wavefront per row folds the
 // shell sum along ky into the row's real trigonometric series in x,
-// a_k cos(k th) + b_k sin(k th), summing modes in a fixed order; the step
-// kernel evaluates that series per node.
+// a_k cos(k th) + b_k sin(k th), th = 2 pi x / nx, summing modes in a fixed
+// order; (3) the synthesis kernel evaluates the series at every node and
+// writes the two force planes the step kernel reads.  Each synthesis thread
+// owns one column, computes its cos/sin(k th) once (exactly reduced
+// sincospi) and sweeps 64 rows, so the per-node cost is 4 FMAs per k.
 #include "internal.hpp"
 #include "device_common.hpp"
 
@@ -48,10 +51,9 @@ __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a) {
     const int j1 = a.bins[k + 1];
     for (int j = a.bins[k]; j < j1; ++j) {
       const int4 md = a.modes[j];
-      // angle 2 pi ky y / ny, reduced exactly in integers
-      const long long num = ((long long)md.z * y) % a.ny;
-      double sn, cs;
-      sincospi(2.0 * (double)num / (double)a.ny, &sn, &cs);
+      // e^{2 pi i ky y / ny} from the phase table, index reduced exactly
+      const double2 e = a.phase[((long long)md.z * y) % a.ny];
+      const double cs = e.x, sn = e.y;
       const double* c = a.coef + 4 * (size_t)md.x;
       const double pxr = 2.0 * (c[0] * cs - c[1] * sn);
       const double pxi = 2.0 * (c[0] * sn + c[1] * cs);
@@ -68,16 +70,47 @@ __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a) {
   a.table[(size_t)y * kTableStride + k] = out;
 }
 
-__global__ __launch_bounds__(256) void stir_field_kernel(
-    const float4* __restrict__ table, int K, float theta_scale, int nx, int ny,
-    float* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nx * ny) return;
-  const int y = i / nx, x = i - y * nx;
-  float fx = 0.f, fy = 0.f;
-  stir_series(table, K, theta_scale, nx, x, y, fx, fy);
-  out[i] = fx;
-  out[(size_t)nx * ny + i] = fy;
+constexpr int kSynthRows = 64;
+
+template <int KB>
+__global__ __launch_bounds__(64) void stir_synth_kernel(const float4* __restrict__ table,
+                                                        float* __restrict__ force,
+                                                        int64_t force_pitch, int K,
+                                                        int nx, int ny) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y0 = blockIdx.y * kSynthRows;
+  const float ts = 2.0f / (float)nx;
+  float c[KB], s[KB];
+#pragma unroll
+  for (int k = 1; k <= KB; ++k) {
+    c[k - 1] = 0.0f;
+    s[k - 1] = 0.0f;
+    if (k <= K) sincospif((float)((k * x) % nx) * ts, &s[k - 1], &c[k - 1]);
+  }
+  if (x >= nx) return;
+  const int y1 = min(y0 + kSynthRows, ny);
+  for (int y = y0; y < y1; ++y) {
+    // the row's coefficients are wave-uniform: scalar loads
+    const float4* __restrict__ row = table + (size_t)y * kTableStride;
+    float4 t = row[0];
+    float fx = t.x, fy = t.z;
+#pragma unroll
+    for (int k = 1; k <= KB; ++k) {
+      t = row[k];   // zero beyond K
+      fx += t.x * c[k - 1] + t.y * s[k - 1];
+      fy += t.z * c[k - 1] + t.w * s[k - 1];
+    }
+    force[(size_t)y * nx + x] = fx;
+    force[force_pitch + (size_t)y * nx + x] = fy;
+  }
+}
+
+__global__ __launch_bounds__(256) void phase_kernel(double2* phase, int ny) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= ny) return;
+  double sn, cs;
+  sincospi(2.0 * (double)m / (double)ny, &sn, &cs);
+  phase[m] = make_double2(cs, sn);
 }
 
 __global__ __launch_bounds__(256) void philox_kernel(uint64_t k0, uint64_t k1,
@@ -107,11 +140,25 @@ hipError_t launch_stir_table(const StirArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stir_field(const rlb_lattice* lat, float* out) {
-  const int ncell = lat->p.nx * lat->p.ny;
-  hipLaunchKernelGGL(stir_field_kernel, dim3((ncell + 255) / 256), dim3(256), 0,
-                     lat->stream, lat->table, lat->K, 2.0f / (float)lat->p.nx,
-                     lat->p.nx, lat->p.ny, out);
+hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s) {
+  const dim3 grid((a.nx + 63) / 64, (a.ny + kSynthRows - 1) / kSynthRows);
+  const float4* t = a.table;
+#define RLB_SYNTH(KB)                                                                  \
+  hipLaunchKernelGGL(stir_synth_kernel<KB>, grid, dim3(64), 0, s, t, a.force, a.force_pitch, \
+                     a.K, a.nx, a.ny)
+  if (a.K <= 8) RLB_SYNTH(8);
+  else if (a.K <= 16) RLB_SYNTH(16);
+  else if (a.K <= 24) RLB_SYNTH(24);
+  else if (a.K <= 34) RLB_SYNTH(34);
+  else if (a.K <= 48) RLB_SYNTH(48);
+  else RLB_SYNTH(63);
+#undef RLB_SYNTH
+  return hipGetLastError();
+}
+
+hipError_t launch_phase(const rlb_lattice* lat) {
+  hipLaunchKernelGGL(phase_kernel, dim3((lat->p.ny + 255) / 256), dim3(256), 0,
+                     lat->stream, lat->phase, lat->p.ny);
   return hipGetLastError();
 }
 

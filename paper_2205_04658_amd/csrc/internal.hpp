@@ -30,23 +30,46 @@ enum StepMode : int { MODE_STEP = 0, MODE_FIELDS = 1 };
 // Force modes: none, uniform body force, body force + k-shell stirring.
 enum ForceMode : int { FORCE_NONE = 0, FORCE_BODY = 1, FORCE_STIR = 2 };
 
-struct StepArgs {
-  const float* src;       // current planes [2Q][pitch] (F then G)
-  float* dst;             // next planes (MODE_STEP)
-  int64_t pitch;          // plane pitch in elements
-  int32_t nx, ny;
-  int32_t tiles_x, ntiles, tiles_per_xcd;
-  const uint8_t* mask;    // [ny][nx] solid flags or null
+// Parameters shared by every lattice of one step launch.
+struct StepShared {
   float tap[kMaxQ][4];    // bilinear weights (w00, w10, w01, w11) per plane
   float inv_tau;
   double eps_ref, n_ref;
   float fx, fy;           // uniform body force
-  const float4* table;    // stirring series table [ny][kMaxK+1]
-  int32_t K;              // stirring series order (largest |kx|)
-  float theta_scale;      // 2 / nx (angle of column x is pi * x * theta_scale)
-  uint32_t* err;
-  float* fields;          // MODE_FIELDS output [k][ny][nx]
-  uint32_t field_mask;
+  uint32_t* err;          // sticky device error word
+  uint32_t field_mask;    // MODE_FIELDS selection
+};
+
+// One lattice as the tile kernel sees it (device memory, read with scalar
+// loads).  state[c] are the two ping-pong copies of the 2Q planes.
+struct LatDesc {
+  const float* state[2];
+  const uint8_t* mask;    // [ny][nx] solid flags (used when MASK)
+  const float* force;     // two stirring-force planes (FORCE_STIR)
+  int64_t pitch;          // plane pitch in elements
+  int32_t nx, ny;
+  int32_t tiles_x;        // tiles per row of tiles
+  int32_t tile_begin;     // first global tile index of this lattice
+  int32_t pad[2];
+};
+
+struct TileArgs {
+  StepShared sh;
+  const LatDesc* lats;
+  const int32_t* tile_lat;  // lattice of each tile; null for a single lattice
+  int32_t parity;           // read state[parity], write state[parity ^ 1]
+  int32_t tile_first;       // tile range of this launch
+  int32_t ntiles;
+  int32_t tiles_per_xcd;    // ceil(ntiles / 8)
+  float* fields;            // MODE_FIELDS output [k][ny][nx]
+};
+
+// Launch shape: tile height in rows (one wavefront per row of 64 nodes) and
+// the grid: 0 = one workgroup per tile, k > 0 = k resident workgroups per CU
+// walking the tile list (persistent).
+struct LaunchShape {
+  int32_t tile_rows;
+  int32_t grid_per_cu;
 };
 
 struct StirArgs {
@@ -54,6 +77,9 @@ struct StirArgs {
   const int32_t* bins;    // [K+2] offsets of |kx| = 0..K in `modes`
   double* coef;           // [nmodes][4] (Re Fx, Im Fx, Re Fy, Im Fy)
   float4* table;          // [ny][kMaxK+1]
+  const double2* phase;   // [ny] (cos, sin)(2 pi m / ny)
+  float* force;           // [2][force_pitch] synthesised force planes
+  int64_t force_pitch;
   int64_t* dstep;         // device step counter (draw reads and advances it)
   int32_t nmodes, K, nx, ny;
   double amplitude;
@@ -62,13 +88,18 @@ struct StirArgs {
 
 struct Workspace {
   size_t state_off[2], mask_off, coef_off, modes_off, bins_off, table_off,
-      partial_off, misc_off, total;
+      phase_off, force_off, partial_off, desc_off, misc_off, total;
 };
 
 }  // namespace rlb
 
 struct rlb_lattice {
   rlb_params p;
+  rlb::LaunchShape shape;
+  rlb::LatDesc desc;      // host copy of the descriptor uploaded to ws
+  rlb::LatDesc* d_desc;
+  int num_cu;
+  struct rlb_batch* owner;  // set when the lattice is a batch member
   int device;
   hipStream_t stream;
   int Q;                  // planes per family (17 or 26)
@@ -84,6 +115,8 @@ struct rlb_lattice {
   int4* modes;
   int32_t* bins;
   float4* table;
+  double2* phase;
+  float* force;
   double* partials;
   uint32_t* err;
   int64_t* dstep;
@@ -109,10 +142,17 @@ struct rlb_lattice {
 
 namespace rlb {
 
+// api.cpp: thread-local message returned by rlb_last_error
+void set_error_message(const char* msg);
+
 // step.hip
+StepShared shared_of(const rlb_lattice* lat);
+hipError_t launch_tiles(int Q, bool unit, bool mask, int mode, int force_mode,
+                        const TileArgs& a, LaunchShape shape, int num_cu,
+                        hipStream_t s);
+int tiles_of(int nx, int ny, int tile_rows);
 hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode,
-                       const float* src, float* dst, float* fields,
-                       uint32_t field_mask);
+                       int parity, float* fields, uint32_t field_mask);
 hipError_t launch_init(const rlb_lattice* lat, const float* eps,
                        const float* bx, const float* by, const float* n,
                        float* dst);
@@ -126,7 +166,8 @@ hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
 hipError_t launch_stir_draw(const StirArgs& a, int64_t fixed_step,
                             hipStream_t s);
 hipError_t launch_stir_table(const StirArgs& a, hipStream_t s);
-hipError_t launch_stir_field(const rlb_lattice* lat, float* out);
+hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s);
+hipError_t launch_phase(const rlb_lattice* lat);
 hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count,
                          uint64_t* out, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);

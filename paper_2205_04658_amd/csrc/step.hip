@@ -5,11 +5,15 @@
 //
 // Layout: 2Q float32 planes [plane][ny][nx] (F planes 0..Q-1, G planes
 // Q..2Q-1), x fastest, plane pitch a multiple of 64 elements.  One thread
-// per node; a 256-thread workgroup covers 64 x 4 nodes and each wavefront
-// one row, so row-uniform quantities (y, the stirring table row) are scalar.
-// Workgroups are mapped to tiles so that each of the eight XCDs walks a
-// contiguous band of tiles: vertically adjacent tiles, which share halo
-// rows, then run on the same XCD and meet in its L2.
+// per node; a tile is 64 x TY nodes, one wavefront per row, so row-uniform
+// quantities are scalar.  A launch walks a list of tiles that may span many
+// lattices (the batched path): each tile names its lattice, whose
+// descriptor is read with scalar loads.  The eight XCDs each take a
+// contiguous band of the tile list, so vertically adjacent tiles, which
+// share halo rows, run on the same XCD and meet in its L2.  The grid is
+// either one workgroup per tile or a persistent set of workgroups per CU.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "device_common.hpp"
 #include "dirset.hpp"
@@ -25,88 +29,116 @@ struct Taps {
   static constexpr bool unit_y = vy == 1.0 || vy == -1.0;
 };
 
-// Pull value of plane P at node (x, y): bilinear interpolation of the
+// Per-lane byte offsets of the 3x3 neighbourhood inside one plane.  Offsets
+// are 32-bit and the plane base is wave-uniform, so every load and store is
+// a scalar-base + vector-offset access with no per-lane 64-bit arithmetic.
+struct Nbr {
+  uint32_t c0, cxm, cxp, ym0, ymxm, ymxp, yp0, ypxm, ypxp;
+};
+
+__device__ __forceinline__ float ld(const float* plane, uint32_t off) {
+  return *(const float*)((const char*)plane + off);
+}
+
+// Pull value of plane P at the node: bilinear interpolation of the
 // pre-stream plane at the departure point (x, y) - cfl (vx, vy).
 template <class DS, bool UNIT, int P>
 __device__ __forceinline__ float pull(const float* __restrict__ pl,
-                                      const StepArgs& a, int r0, int rm,
-                                      int rp, int x, int xm, int xp) {
+                                      const StepShared& a, const Nbr& n) {
   using T = Taps<DS, P>;
-  const int xs = T::sx > 0 ? xm : xp;      // column x - sx
-  const int rs = T::sy > 0 ? rm : rp;      // row y - sy
+  const uint32_t c_x = T::sx > 0 ? n.cxm : n.cxp;              // (x - sx, y)
+  const uint32_t c_y = T::sy > 0 ? n.ym0 : n.yp0;              // (x, y - sy)
+  const uint32_t c_xy = T::sy > 0 ? (T::sx > 0 ? n.ymxm : n.ymxp)
+                                  : (T::sx > 0 ? n.ypxm : n.ypxp);
   if constexpr (T::sx == 0 && T::sy == 0) {
-    return pl[r0 + x];
+    return ld(pl, n.c0);
   } else if constexpr (UNIT && T::unit_x) {
-    return pl[r0 + xs];                    // full step along x
+    return ld(pl, c_x);                    // full step along x
   } else if constexpr (UNIT && T::unit_y) {
-    return pl[rs + x];                     // full step along y
+    return ld(pl, c_y);                    // full step along y
   } else if constexpr (T::sy == 0) {
-    return a.tap[P][0] * pl[r0 + x] + a.tap[P][1] * pl[r0 + xs];
+    return a.tap[P][0] * ld(pl, n.c0) + a.tap[P][1] * ld(pl, c_x);
   } else if constexpr (T::sx == 0) {
-    return a.tap[P][0] * pl[r0 + x] + a.tap[P][2] * pl[rs + x];
+    return a.tap[P][0] * ld(pl, n.c0) + a.tap[P][2] * ld(pl, c_y);
   } else {
-    return a.tap[P][0] * pl[r0 + x] + a.tap[P][1] * pl[r0 + xs] +
-           a.tap[P][2] * pl[rs + x] + a.tap[P][3] * pl[rs + xs];
+    return a.tap[P][0] * ld(pl, n.c0) + a.tap[P][1] * ld(pl, c_x) +
+           a.tap[P][2] * ld(pl, c_y) + a.tap[P][3] * ld(pl, c_xy);
   }
 }
 
-template <class DS, bool UNIT, bool MASK, int FORCE, int MODE>
-__global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a) {
-  constexpr int Q = DS::Q;
-  const int hw = blockIdx.x;
-  const int tile = (hw & 7) * a.tiles_per_xcd + (hw >> 3);
-  if (tile >= a.ntiles) return;
-  const int ty = tile / a.tiles_x;
-  const int tx = tile - ty * a.tiles_x;
-  const int x = tx * kTileX + (threadIdx.x & (kTileX - 1));
-  const int y = __builtin_amdgcn_readfirstlane(ty * kTileY + (threadIdx.x >> 6));
-  if (x >= a.nx || y >= a.ny) return;
+__device__ __forceinline__ void st(float* plane, uint32_t off, float v) {
+  __builtin_nontemporal_store(v, (float*)((char*)plane + off));
+}
 
-  const int nx = a.nx, ny = a.ny;
+template <class DS, bool UNIT, bool MASK, int FORCE, int MODE>
+__device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc& L,
+                                            const float* __restrict__ src,
+                                            float* __restrict__ dst,
+                                            float* __restrict__ fields, int x, int y) {
+  constexpr int Q = DS::Q;
+  const int nx = L.nx, ny = L.ny;
+  const int64_t pitch = L.pitch;
   const int xm = x == 0 ? nx - 1 : x - 1;
   const int xp = x == nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? ny - 1 : y - 1;
   const int yp = y == ny - 1 ? 0 : y + 1;
-  const int r0 = y * nx, rm = ym * nx, rp = yp * nx;
-  const int node = r0 + x;
+  const uint32_t r0 = (uint32_t)(y * nx), rm = (uint32_t)(ym * nx), rp = (uint32_t)(yp * nx);
+  Nbr nb;
+  nb.c0 = 4u * (r0 + x);   nb.cxm = 4u * (r0 + xm); nb.cxp = 4u * (r0 + xp);
+  nb.ym0 = 4u * (rm + x);  nb.ymxm = 4u * (rm + xm); nb.ymxp = 4u * (rm + xp);
+  nb.yp0 = 4u * (rp + x);  nb.ypxm = 4u * (rp + xm); nb.ypxp = 4u * (rp + xp);
+  const uint32_t node = r0 + (uint32_t)x;
+  const StepShared& a = sh;
 
   // 1. pull-stream every plane
   float f[Q], g[Q];
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
-    f[p] = pull<DS, UNIT, p>(a.src + p * a.pitch, a, r0, rm, rp, x, xm, xp);
-    g[p] = pull<DS, UNIT, p>(a.src + (Q + p) * a.pitch, a, r0, rm, rp, x, xm, xp);
+    f[p] = pull<DS, UNIT, p>(src + p * pitch, a, nb);
+    g[p] = pull<DS, UNIT, p>(src + (Q + p) * pitch, a, nb);
   });
 
   bool solid = false;
-  if constexpr (MASK) solid = a.mask[node] != 0;
+  if constexpr (MASK) solid = L.mask[node] != 0;
 
   if constexpr (MODE == MODE_STEP) {
     if (solid) {   // bounce-back: F'_i = F~_opp(i)
       static_for<0, Q>([&](auto P) {
         constexpr int p = decltype(P)::value;
-        __builtin_nontemporal_store(f[DS::opp[p]], a.dst + p * a.pitch + node);
-        __builtin_nontemporal_store(g[DS::opp[p]], a.dst + (Q + p) * a.pitch + node);
+        st(dst + p * pitch, nb.c0, f[DS::opp[p]]);
+        st(dst + (Q + p) * pitch, nb.c0, g[DS::opp[p]]);
       });
       return;
     }
   }
 
-  // 2. moments of the deviations from the reference (float32 sums of small
-  //    numbers), then the reference added in float64
+  // 2. moments of the deviations from the reference: float32 sums over
+  //    opposite pairs (even moments from f_a + f_b, odd from f_a - f_b),
+  //    then the reference added in float64
   float m00 = 0, m0x = 0, m0y = 0, mxx = 0, mxy = 0, myy = 0;
   float j0 = 0, jx = 0, jy = 0;
+  float df[Q];   // f_a - f_b of each pair head a (odd parts), reused by the force
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
-    constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
-    m00 += f[p];
-    j0 += g[p];
-    constexpr float vxx = (float)(DS::vx[p] * DS::vx[p]);
-    constexpr float vyy = (float)(DS::vy[p] * DS::vy[p]);
-    constexpr float vxy = (float)(DS::vx[p] * DS::vy[p]);
-    if constexpr (DS::vx[p] != 0.0) { m0x += vx * f[p]; jx += vx * g[p]; mxx += vxx * f[p]; }
-    if constexpr (DS::vy[p] != 0.0) { m0y += vy * f[p]; jy += vy * g[p]; myy += vyy * f[p]; }
-    if constexpr (DS::vx[p] != 0.0 && DS::vy[p] != 0.0) mxy += vxy * f[p];
+    constexpr int q = DS::opp[p];
+    if constexpr (q == p) {
+      m00 += f[p];
+      j0 += g[p];
+    } else if constexpr (q > p) {
+      constexpr double vx = DS::vx[p], vy = DS::vy[p];
+      const float sf = f[p] + f[q], sg = g[p] + g[q];
+      df[p] = f[p] - f[q];
+      const float dg = g[p] - g[q];
+      m00 += sf;
+      j0 += sg;
+      if constexpr (vx != 0.0) {
+        m0x += (float)vx * df[p]; jx += (float)vx * dg; mxx += (float)(vx * vx) * sf;
+      }
+      if constexpr (vy != 0.0) {
+        m0y += (float)vy * df[p]; jy += (float)vy * dg; myy += (float)(vy * vy) * sf;
+      }
+      if constexpr (vx != 0.0 && vy != 0.0) mxy += (float)(vx * vy) * sf;
+    }
   });
   const double T00 = a.eps_ref + (double)m00;
   const double T0x = (double)m0x, T0y = (double)m0y;
@@ -131,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a) {
 #pragma unroll
     for (int fld = 0; fld < RLB_FIELD_COUNT; ++fld) {
       if (a.field_mask & (1u << fld)) {
-        a.fields[k * plane + node] = (solid || !ok) ? 0.0f : (float)vals[fld];
+        fields[k * plane + node] = (solid || !ok) ? 0.0f : (float)vals[fld];
         ++k;
       }
     }
@@ -141,39 +173,43 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a) {
       atomicOr(a.err, ERR_LANDAU);
       static_for<0, Q>([&](auto P) {
         constexpr int p = decltype(P)::value;
-        a.dst[p * a.pitch + node] = f[p];
-        a.dst[(Q + p) * a.pitch + node] = g[p];
+        st(dst + p * pitch, nb.c0, f[p]);
+        st(dst + (Q + p) * pitch, nb.c0, g[p]);
       });
       return;
     }
 
     // 4. equilibrium and collision-rate coefficients
-    const EqCoef ec = eq_coef(fr, n, a.eps_ref, a.n_ref);
+    const EqCoef ec = eq_coef(fr, n, a.eps_ref, a.n_ref, DS::kappa);
     const float ux = (float)fr.ux, uy = (float)fr.uy;
     const float w0 = (float)fr.u0 * a.inv_tau;
-    const float wx = ux * a.inv_tau, wy = uy * a.inv_tau;
 
-    // 5. driving term coefficients: Phi(v) = p0 + px vx + py vy + pxx vx^2
-    //    + pxy vx vy + pyy vy^2 (vz^2 = 1 - vx^2 - vy^2 folded in)
+    // 5. driving term Phi(v) = p0 + px vx + py vy + pxx vx^2 + pxy vx vy
+    //    + pyy vy^2 (vz^2 = 1 - vx^2 - vy^2 folded in)
     float p0 = 0, px = 0, py = 0, pxx = 0, pxy = 0, pyy = 0;
     if constexpr (FORCE != FORCE_NONE) {
       float Fx = a.fx, Fy = a.fy;
-      if constexpr (FORCE == FORCE_STIR) stir_series(a.table, a.K, a.theta_scale, nx, x, y, Fx, Fy);
+      if constexpr (FORCE == FORCE_STIR) {
+        Fx += ld(L.force, nb.c0);
+        Fy += ld(L.force + pitch, nb.c0);
+      }
       float q3xxx = 0, q3xxy = 0, q3xyy = 0, q3yyy = 0, q3xzz = 0, q3yzz = 0;
       static_for<0, Q>([&](auto P) {
         constexpr int p = decltype(P)::value;
-        constexpr double vx = DS::vx[p], vy = DS::vy[p], vz2 = DS::vz2[p];
-        if constexpr (vx != 0.0) {
-          q3xxx += (float)(vx * vx * vx) * f[p];
-          if constexpr (vz2 != 0.0) q3xzz += (float)(vx * vz2) * f[p];
-        }
-        if constexpr (vy != 0.0) {
-          q3yyy += (float)(vy * vy * vy) * f[p];
-          if constexpr (vz2 != 0.0) q3yzz += (float)(vy * vz2) * f[p];
-        }
-        if constexpr (vx != 0.0 && vy != 0.0) {
-          q3xxy += (float)(vx * vx * vy) * f[p];
-          q3xyy += (float)(vx * vy * vy) * f[p];
+        if constexpr (DS::opp[p] > p) {   // third moments are odd
+          constexpr double vx = DS::vx[p], vy = DS::vy[p], vz2 = DS::vz2[p];
+          if constexpr (vx != 0.0) {
+            q3xxx += (float)(vx * vx * vx) * df[p];
+            if constexpr (vz2 != 0.0) q3xzz += (float)(vx * vz2) * df[p];
+          }
+          if constexpr (vy != 0.0) {
+            q3yyy += (float)(vy * vy * vy) * df[p];
+            if constexpr (vz2 != 0.0) q3yzz += (float)(vy * vz2) * df[p];
+          }
+          if constexpr (vx != 0.0 && vy != 0.0) {
+            q3xxy += (float)(vx * vx * vy) * df[p];
+            q3xyy += (float)(vx * vy * vy) * df[p];
+          }
         }
       });
       const float M0 = (float)T00, M1x = (float)T0x, M1y = (float)T0y;
@@ -191,24 +227,67 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a) {
       pyy = 1.25f * Qyy - 2.5f * Fy * M1y - pzz;
     }
 
-    // 6. relax and drive, store
+    // 6. relax and drive, per opposite pair (a, b) with v_b = -v_a: the
+    //    equilibrium, rate and driving term split into even and odd parts
+    //    in s = u.v_a
     static_for<0, Q>([&](auto P) {
       constexpr int p = decltype(P)::value;
-      constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
-      constexpr float w = (float)DS::w[p];
-      const float s = ux * vx + uy * vy;
-      const float om = w0 - (wx * vx + wy * vy);
-      const float feq = w * (ec.A + s * (ec.B + s * ec.C));
-      const float geq = w * (ec.Ag + s * ec.Bg);
-      float fn = f[p] - om * (f[p] - feq);
-      if constexpr (FORCE != FORCE_NONE) {
-        const float phi = p0 + vx * (px + vx * pxx + vy * pxy) + vy * (py + vy * pyy);
-        fn -= w * phi;
+      constexpr int q = DS::opp[p];
+      constexpr float w = DS::w32[p];
+      if constexpr (q == p) {
+        const float fn = f[p] - w0 * (f[p] - w * ec.A) - w * p0;
+        const float gn = g[p] - w0 * (g[p] - w * ec.Ag);
+        st(dst + p * pitch, nb.c0, fn);
+        st(dst + (Q + p) * pitch, nb.c0, gn);
+      } else if constexpr (q > p) {
+        constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
+        constexpr float vxx = (float)(DS::vx[p] * DS::vx[p]);
+        constexpr float vyy = (float)(DS::vy[p] * DS::vy[p]);
+        constexpr float vxy = (float)(DS::vx[p] * DS::vy[p]);
+        const float s = ux * vx + uy * vy;
+        const float t = s * a.inv_tau;
+        const float e0 = w * (ec.A + ec.C * s * s), e1 = w * (ec.B * s);
+        const float g0 = w * ec.Ag, g1 = w * (ec.Bg * s);
+        const float oa = w0 - t, ob = w0 + t;
+        float fa = f[p] - oa * (f[p] - (e0 + e1));
+        float fb = f[q] - ob * (f[q] - (e0 - e1));
+        if constexpr (FORCE != FORCE_NONE) {
+          const float pe = w * (p0 + vxx * pxx + vxy * pxy + vyy * pyy);
+          const float po = w * (vx * px + vy * py);
+          fa -= pe + po;
+          fb -= pe - po;
+        }
+        const float ga = g[p] - oa * (g[p] - (g0 + g1));
+        const float gb = g[q] - ob * (g[q] - (g0 - g1));
+        st(dst + p * pitch, nb.c0, fa);
+        st(dst + q * pitch, nb.c0, fb);
+        st(dst + (Q + p) * pitch, nb.c0, ga);
+        st(dst + (Q + q) * pitch, nb.c0, gb);
       }
-      const float gn = g[p] - om * (g[p] - geq);
-      __builtin_nontemporal_store(fn, a.dst + p * a.pitch + node);
-      __builtin_nontemporal_store(gn, a.dst + (Q + p) * a.pitch + node);
     });
+  }
+}
+
+template <class DS, bool UNIT, bool MASK, int FORCE, int MODE, int TY>
+__global__ __launch_bounds__(64 * TY) void tile_kernel(const TileArgs a) {
+  const int xcd = blockIdx.x & 7;
+  const int per = gridDim.x >> 3;
+  const int lo = xcd * a.tiles_per_xcd;
+  const int hi = min(lo + a.tiles_per_xcd, a.ntiles);
+  const int lane = threadIdx.x & 63;
+  const int row = threadIdx.x >> 6;
+  for (int t = lo + (int)(blockIdx.x >> 3); t < hi; t += per) {
+    const int tile = a.tile_first + t;
+    const int b = a.tile_lat ? a.tile_lat[tile] : 0;
+    const LatDesc& L = a.lats[b];
+    const int lt = tile - L.tile_begin;
+    const int ty = lt / L.tiles_x;
+    const int x = (lt - ty * L.tiles_x) * 64 + lane;
+    const int y = __builtin_amdgcn_readfirstlane(ty * TY + row);
+    if (x < L.nx && y < L.ny)
+      node_update<DS, UNIT, MASK, FORCE, MODE>(a.sh, L, L.state[a.parity],
+                                               const_cast<float*>(L.state[a.parity ^ 1]),
+                                               a.fields, x, y);
   }
 }
 
@@ -225,12 +304,12 @@ __global__ __launch_bounds__(256) void init_kernel(
     atomicOr(err, ERR_LANDAU);
     fr.eps = eps_ref; fr.u0 = 1.0; fr.ux = 0.0; fr.uy = 0.0;
   }
-  const EqCoef ec = eq_coef(fr, (double)nn[i], eps_ref, n_ref);
+  const EqCoef ec = eq_coef(fr, (double)nn[i], eps_ref, n_ref, DS::kappa);
   const float ux = (float)fr.ux, uy = (float)fr.uy;
   static_for<0, DS::Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
     constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
-    constexpr float w = (float)DS::w[p];
+    constexpr float w = DS::w32[p];
     const float s = ux * vx + uy * vy;
     dst[p * pitch + i] = w * (ec.A + s * (ec.B + s * ec.C));
     dst[(DS::Q + p) * pitch + i] = w * (ec.Ag + s * ec.Bg);
@@ -285,15 +364,8 @@ __global__ __launch_bounds__(256) void fill_u8_kernel(uint8_t* p, size_t n,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static void fill_args(const rlb_lattice* lat, StepArgs& a) {
-  const int nx = lat->p.nx, ny = lat->p.ny;
-  a.pitch = lat->pitch;
-  a.nx = nx;
-  a.ny = ny;
-  a.tiles_x = (nx + kTileX - 1) / kTileX;
-  a.ntiles = a.tiles_x * ((ny + kTileY - 1) / kTileY);
-  a.tiles_per_xcd = (a.ntiles + 7) / 8;
-  a.mask = lat->any_solid ? lat->mask : nullptr;
+StepShared shared_of(const rlb_lattice* lat) {
+  StepShared a;
   for (int p = 0; p < kMaxQ; ++p)
     for (int c = 0; c < 4; ++c) a.tap[p][c] = lat->tap[p][c];
   a.inv_tau = (float)(1.0 / lat->p.tau);
@@ -301,66 +373,92 @@ static void fill_args(const rlb_lattice* lat, StepArgs& a) {
   a.n_ref = lat->p.n_ref;
   a.fx = (float)lat->fx;
   a.fy = (float)lat->fy;
-  a.table = lat->table;
-  a.K = lat->K;
-  a.theta_scale = 2.0f / (float)nx;
   a.err = lat->err;
+  a.field_mask = 0;
+  return a;
 }
 
-template <class DS, bool UNIT, bool MASK, int MODE>
-static hipError_t dispatch_force(int force, const StepArgs& a, dim3 grid,
-                                 hipStream_t s) {
-  if constexpr (MODE == MODE_FIELDS) {
-    hipLaunchKernelGGL((step_kernel<DS, UNIT, MASK, FORCE_NONE, MODE>), grid,
-                       dim3(kBlock), 0, s, a);
-  } else {
-    switch (force) {
-      case FORCE_NONE:
-        hipLaunchKernelGGL((step_kernel<DS, UNIT, MASK, FORCE_NONE, MODE>),
-                           grid, dim3(kBlock), 0, s, a);
-        break;
-      case FORCE_BODY:
-        hipLaunchKernelGGL((step_kernel<DS, UNIT, MASK, FORCE_BODY, MODE>),
-                           grid, dim3(kBlock), 0, s, a);
-        break;
-      default:
-        hipLaunchKernelGGL((step_kernel<DS, UNIT, MASK, FORCE_STIR, MODE>),
-                           grid, dim3(kBlock), 0, s, a);
-        break;
+int tiles_of(int nx, int ny, int tile_rows) {
+  return ((nx + 63) / 64) * ((ny + tile_rows - 1) / tile_rows);
+}
+
+template <class DS, bool UNIT, bool MASK, int FORCE, int MODE, int TY>
+static void go(const TileArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((tile_kernel<DS, UNIT, MASK, FORCE, MODE, TY>), dim3(grid),
+                     dim3(64 * TY), 0, s, a);
+}
+
+// Tile heights other than 4 are compiled for the folded set's step kernels
+// only (the autotuner's search space); everything else uses 4.
+template <class DS, bool UNIT, bool MASK, int FORCE, int MODE>
+static void by_rows(int ty, const TileArgs& a, int grid, hipStream_t s) {
+  if constexpr (DS::Q == 17 && MODE == MODE_STEP) {
+    switch (ty) {
+      case 1: go<DS, UNIT, MASK, FORCE, MODE, 1>(a, grid, s); return;
+      case 2: go<DS, UNIT, MASK, FORCE, MODE, 2>(a, grid, s); return;
+      case 8: go<DS, UNIT, MASK, FORCE, MODE, 8>(a, grid, s); return;
+      default: break;
     }
   }
-  return hipGetLastError();
+  go<DS, UNIT, MASK, FORCE, MODE, 4>(a, grid, s);
+}
+
+template <class DS, bool UNIT, bool MASK>
+static void by_force(int mode, int force, int ty, const TileArgs& a, int grid, hipStream_t s) {
+  if (mode == MODE_FIELDS) return by_rows<DS, UNIT, MASK, FORCE_NONE, MODE_FIELDS>(4, a, grid, s);
+  if (force == FORCE_NONE) return by_rows<DS, UNIT, MASK, FORCE_NONE, MODE_STEP>(ty, a, grid, s);
+  if (force == FORCE_BODY) return by_rows<DS, UNIT, MASK, FORCE_BODY, MODE_STEP>(ty, a, grid, s);
+  by_rows<DS, UNIT, MASK, FORCE_STIR, MODE_STEP>(ty, a, grid, s);
 }
 
 template <class DS>
-static hipError_t dispatch(bool unit, bool mask, int mode, int force,
-                           const StepArgs& a, dim3 grid, hipStream_t s) {
-  if (mode == MODE_FIELDS) {
-    if (unit) return mask ? dispatch_force<DS, true, true, MODE_FIELDS>(force, a, grid, s)
-                          : dispatch_force<DS, true, false, MODE_FIELDS>(force, a, grid, s);
-    return mask ? dispatch_force<DS, false, true, MODE_FIELDS>(force, a, grid, s)
-                : dispatch_force<DS, false, false, MODE_FIELDS>(force, a, grid, s);
+static void by_flags(bool unit, bool mask, int mode, int force, int ty, const TileArgs& a,
+                     int grid, hipStream_t s) {
+  if (unit) {
+    if (mask) by_force<DS, true, true>(mode, force, ty, a, grid, s);
+    else by_force<DS, true, false>(mode, force, ty, a, grid, s);
+  } else {
+    if (mask) by_force<DS, false, true>(mode, force, ty, a, grid, s);
+    else by_force<DS, false, false>(mode, force, ty, a, grid, s);
   }
-  if (unit) return mask ? dispatch_force<DS, true, true, MODE_STEP>(force, a, grid, s)
-                        : dispatch_force<DS, true, false, MODE_STEP>(force, a, grid, s);
-  return mask ? dispatch_force<DS, false, true, MODE_STEP>(force, a, grid, s)
-              : dispatch_force<DS, false, false, MODE_STEP>(force, a, grid, s);
 }
 
-hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode,
-                       const float* src, float* dst, float* fields,
-                       uint32_t field_mask) {
-  StepArgs a;
-  fill_args(lat, a);
-  a.src = src;
-  a.dst = dst;
+hipError_t launch_tiles(int Q, bool unit, bool mask, int mode, int force_mode,
+                        const TileArgs& a0, LaunchShape shape, int num_cu, hipStream_t s) {
+  if (a0.ntiles <= 0) return hipSuccess;
+  TileArgs a = a0;
+  int ty = shape.tile_rows;
+  if (!(Q == 17 && mode == MODE_STEP)) ty = 4;
+  a.tiles_per_xcd = (a.ntiles + 7) / 8;
+  int grid;
+  if (shape.grid_per_cu <= 0) {
+    grid = 8 * a.tiles_per_xcd;
+  } else {
+    // resident workgroups, rounded to a multiple of the 8 XCDs
+    grid = std::max(8, (num_cu * shape.grid_per_cu * 4 / ty) / 8 * 8);
+    grid = std::min(grid, 8 * a.tiles_per_xcd);
+  }
+  if (Q == 17) by_flags<Dir17>(unit, mask, mode, force_mode, ty, a, grid, s);
+  else by_flags<Dir26>(unit, mask, mode, force_mode, ty, a, grid, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode, int parity,
+                       float* fields, uint32_t field_mask) {
+  TileArgs a;
+  a.sh = shared_of(lat);
+  a.sh.field_mask = field_mask;
+  a.lats = lat->d_desc;
+  a.tile_lat = nullptr;
+  a.parity = parity;
+  a.tile_first = 0;
+  const int ty = (mode == MODE_STEP && lat->Q == 17) ? lat->shape.tile_rows : 4;
+  a.ntiles = tiles_of(lat->p.nx, lat->p.ny, ty);
   a.fields = fields;
-  a.field_mask = field_mask;
-  const dim3 grid(8 * a.tiles_per_xcd);
-  const bool unit = lat->p.cfl == 1.0;
-  const bool mask = a.mask != nullptr;
-  if (lat->Q == 17) return dispatch<Dir17>(unit, mask, mode, force_mode, a, grid, lat->stream);
-  return dispatch<Dir26>(unit, mask, mode, force_mode, a, grid, lat->stream);
+  LaunchShape sh = lat->shape;
+  if (mode != MODE_STEP) sh.grid_per_cu = 0;
+  return launch_tiles(lat->Q, lat->p.cfl == 1.0, lat->any_solid, mode, force_mode, a, sh,
+                      lat->num_cu, lat->stream);
 }
 
 hipError_t launch_init(const rlb_lattice* lat, const float* eps,

@@ -28,6 +28,11 @@ SYMBOLS = [
     "rlb_get_step", "rlb_state_bytes", "rlb_save_state", "rlb_load_state", "rlb_layout",
     "rlb_stirring_coefficients", "rlb_stirring_field", "rlb_philox", "rlb_timing",
     "rlb_timing_read", "rlb_copy_probe", "rlb_last_error", "rlb_version",
+    "rlb_set_launch_shape", "rlb_get_launch_shape", "rlb_autotune",
+    "rlb_batch_workspace_bytes", "rlb_batch_create", "rlb_batch_destroy", "rlb_batch_member",
+    "rlb_batch_set_body_force", "rlb_batch_step", "rlb_batch_sync", "rlb_batch_info",
+    "rlb_batch_set_launch_shape", "rlb_batch_get_launch_shape", "rlb_batch_autotune",
+    "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
 ]
 
 
@@ -84,6 +89,23 @@ def lib():
         "rlb_timing": [_vp, _i32],
         "rlb_timing_read": [_vp, _P(_d), _P(_i64)],
         "rlb_copy_probe": [_vp, _vp, _sz, _vp],
+        "rlb_set_launch_shape": [_vp, _i32, _i32],
+        "rlb_get_launch_shape": [_vp, _P(_i32), _P(_i32)],
+        "rlb_autotune": [_vp, _i32, _P(_d), _i32],
+        "rlb_batch_workspace_bytes": [_P(Params), _i32, _vp, _vp, _P(_sz)],
+        "rlb_batch_create": [_P(Params), _i32, _vp, _vp, _vp, _sz, _vp, _P(_vp)],
+        "rlb_batch_destroy": [_vp],
+        "rlb_batch_member": [_vp, _i32, _P(_vp)],
+        "rlb_batch_set_body_force": [_vp, _d, _d],
+        "rlb_batch_step": [_vp, _i64],
+        "rlb_batch_sync": [_vp],
+        "rlb_batch_info": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_i64)],
+        "rlb_batch_set_launch_shape": [_vp, _i32, _i32],
+        "rlb_batch_get_launch_shape": [_vp, _P(_i32), _P(_i32)],
+        "rlb_batch_autotune": [_vp, _i32, _P(_d), _i32],
+        "rlb_batch_use_graph": [_vp, _i32],
+        "rlb_batch_timing": [_vp, _i32],
+        "rlb_batch_timing_read": [_vp, _P(_d), _P(_i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -149,8 +171,14 @@ class Lattice:
     this object; all work goes to the torch stream current at creation."""
 
     def __init__(self, nx, ny, tau, cfl=1.0, walls=False, full26=False,
-                 eps_ref=1.0, n_ref=0.1, device=None):
+                 eps_ref=1.0, n_ref=0.1, device=None, _member=None):
         torch = _torch()
+        if _member is not None:          # a batch member: handle owned by the batch
+            batch, h = _member
+            self.nx, self.ny = int(nx), int(ny)
+            self.device, self.stream, self.workspace = batch.device, batch.stream, None
+            self._h, self._owned, self._batch, self._keep = h, False, batch, []
+            return
         self.nx, self.ny = int(nx), int(ny)
         flags = (WALLS_Y if walls else 0) | (FULL26 if full26 else 0)
         self.params = Params(self.nx, self.ny, float(tau), float(cfl), flags,
@@ -164,13 +192,31 @@ class Lattice:
         check(lib().rlb_create(ctypes.byref(self.params), _vp(self.workspace.data_ptr()), n.value,
                                _stream_ptr(self.stream), ctypes.byref(h)))
         self._h = h
+        self._owned = True
         self._keep = []
+
+    # -- streams ------------------------------------------------------------
+    def _in(self, *tensors):
+        """Order the lattice stream after the caller's stream (inputs ready)."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+            for t in tensors:
+                t.record_stream(self.stream)
+
+    def _out(self):
+        """Order the caller's stream after the lattice stream (outputs ready)."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owned", False):
             lib().rlb_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -182,6 +228,7 @@ class Lattice:
     def init_fields(self, eps, bx, by, n):
         shape = (self.ny, self.nx)
         ts = [_dev_f32(a, self.device, shape) for a in (eps, bx, by, n)]
+        self._in(*ts)
         check(lib().rlb_init_fields(self._h, *[_vp(t.data_ptr()) for t in ts]))
         self._keep = ts
 
@@ -189,6 +236,7 @@ class Lattice:
         torch = _torch()
         m = torch.as_tensor(np.asarray(mask) if not isinstance(mask, torch.Tensor) else mask)
         m = m.to(device=self.device, dtype=torch.uint8).contiguous()
+        self._in(m)
         check(lib().rlb_set_obstacles(self._h, _vp(m.data_ptr())))
         self._keep = [m]
 
@@ -228,7 +276,9 @@ class Lattice:
             mask |= 1 << FIELDS.index(nm)
         order = [f for f in FIELDS if mask & (1 << FIELDS.index(f))]
         out = torch.empty((len(order), self.ny, self.nx), dtype=torch.float32, device=self.device)
+        self._in(out)
         check(lib().rlb_read_fields(self._h, mask, _vp(out.data_ptr())))
+        self._out()
         return {nm: out[i] for i, nm in enumerate(order)}
 
     def conserved(self):
@@ -246,10 +296,13 @@ class Lattice:
         n = _sz()
         check(lib().rlb_state_bytes(self._h, ctypes.byref(n)))
         buf = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self._in(buf)
         check(lib().rlb_save_state(self._h, _vp(buf.data_ptr()), n.value))
+        self._out()
         return buf
 
     def load_state(self, buf):
+        self._in(buf)
         check(lib().rlb_load_state(self._h, _vp(buf.data_ptr()), buf.numel()))
 
     def planes(self, buf=None):
@@ -276,10 +329,121 @@ class Lattice:
         check(lib().rlb_stirring_field(self._h, int(step), _vp(out.data_ptr())))
         return out
 
+    def set_launch_shape(self, tile_rows, grid_per_cu):
+        check(lib().rlb_set_launch_shape(self._h, int(tile_rows), int(grid_per_cu)))
+
+    def launch_shape(self):
+        a, b = _i32(), _i32()
+        check(lib().rlb_get_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, trials=5):
+        """Time every launch shape on the current state (which does not
+        advance), keep the fastest; returns [(tile_rows, grid_per_cu, ms)]."""
+        out = (_d * (3 * 64))()
+        check(lib().rlb_autotune(self._h, int(trials), out, 64))
+        rows = [(int(out[3 * i]), int(out[3 * i + 1]), out[3 * i + 2]) for i in range(64)]
+        return [r for r in rows if r[2] > 0]
+
     def timing(self, enable=True):
         check(lib().rlb_timing(self._h, 1 if enable else 0))
 
     def timing_read(self):
         ms, n = _d(), _i64()
         check(lib().rlb_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+class Batch:
+    """Many lattices of uneven sizes advanced by one launch per step (hipGraph
+    replay on a dedicated stream).  `sizes` is a list of (nx, ny); members
+    are Lattice objects (`batch[b]`) for initialisation and read-out."""
+
+    def __init__(self, sizes, tau, cfl=1.0, walls=False, full26=False, eps_ref=1.0,
+                 n_ref=0.1, device=None):
+        torch = _torch()
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        n = len(self.sizes)
+        flags = (WALLS_Y if walls else 0) | (FULL26 if full26 else 0)
+        self.params = Params(0, 0, float(tau), float(cfl), flags, float(eps_ref), float(n_ref))
+        self._nx = (_i32 * n)(*[a for a, _ in self.sizes])
+        self._ny = (_i32 * n)(*[b for _, b in self.sizes])
+        nb = _sz()
+        check(lib().rlb_batch_workspace_bytes(ctypes.byref(self.params), n, self._nx, self._ny,
+                                              ctypes.byref(nb)))
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = torch.cuda.Stream(self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        h = _vp()
+        check(lib().rlb_batch_create(ctypes.byref(self.params), n, self._nx, self._ny,
+                                     _vp(self.workspace.data_ptr()), nb.value,
+                                     _stream_ptr(self.stream), ctypes.byref(h)))
+        self._h = h
+        self.members = []
+        for b, (a, c) in enumerate(self.sizes):
+            mh = _vp()
+            check(lib().rlb_batch_member(self._h, b, ctypes.byref(mh)))
+            self.members.append(Lattice(a, c, tau, _member=(self, mh)))
+
+    def __getitem__(self, b):
+        return self.members[b]
+
+    def __len__(self):
+        return len(self.members)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for m in self.members:
+                m._h = None
+            lib().rlb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_body_force(self, fx, fy=0.0):
+        check(lib().rlb_batch_set_body_force(self._h, float(fx), float(fy)))
+
+    def step(self, n=1):
+        torch = _torch()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        check(lib().rlb_batch_step(self._h, int(n)))
+
+    def sync(self):
+        check(lib().rlb_batch_sync(self._h))
+
+    def info(self):
+        c, cells, q, st = _i32(), _i64(), _i32(), _i64()
+        check(lib().rlb_batch_info(self._h, ctypes.byref(c), ctypes.byref(cells), ctypes.byref(q),
+                                   ctypes.byref(st)))
+        return dict(count=c.value, cells=cells.value, planes=q.value, step=st.value)
+
+    def set_launch_shape(self, tile_rows, grid_per_cu):
+        check(lib().rlb_batch_set_launch_shape(self._h, int(tile_rows), int(grid_per_cu)))
+
+    def launch_shape(self):
+        a, b = _i32(), _i32()
+        check(lib().rlb_batch_get_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, trials=5):
+        out = (_d * (3 * 64))()
+        check(lib().rlb_batch_autotune(self._h, int(trials), out, 64))
+        rows = [(int(out[3 * i]), int(out[3 * i + 1]), out[3 * i + 2]) for i in range(64)]
+        return [r for r in rows if r[2] > 0]
+
+    def use_graph(self, steps_per_graph=16):
+        check(lib().rlb_batch_use_graph(self._h, int(steps_per_graph)))
+
+    def timing(self, enable=True):
+        check(lib().rlb_batch_timing(self._h, 1 if enable else 0))
+
+    def timing_read(self):
+        ms, n = _d(), _i64()
+        check(lib().rlb_batch_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value

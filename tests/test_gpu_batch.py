@@ -1,0 +1,124 @@
+"""Batched lattices (one launch per step over many lattices, hipGraph replay)
+and launch shapes: every member evolves bitwise as the same lattice stepped
+alone, for every launch shape, with or without graphs."""
+import numpy as np
+import pytest
+
+from paper_2205_04658_amd import workloads
+from rlbtest import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(70, 40), (128, 64), (65, 33), (200, 19)]
+TAU = 0.8
+FB = (2e-4, 0.0)
+
+
+def setup_member(lat, b, nx, ny):
+    f = workloads.random_fields(nx, ny, seed=100 + b, beta=0.02)
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    discs = workloads.channel_discs(nx, ny, 4.0, 0.05, seed=7, stream=b)
+    lat.add_disks(discs)
+
+
+def single_runs(steps, shape=None):
+    from paper_2205_04658_amd.rlb import Lattice
+    out = []
+    for b, (nx, ny) in enumerate(SIZES):
+        lat = Lattice(nx, ny, TAU, walls=True)
+        if shape:
+            lat.set_launch_shape(*shape)
+        setup_member(lat, b, nx, ny)
+        lat.set_body_force(*FB)
+        lat.step(steps)
+        lat.sync()
+        f, g = lat.planes()
+        out.append((f.cpu(), g.cpu()))
+    return out
+
+
+def make_batch():
+    from paper_2205_04658_amd.rlb import Batch
+    B = Batch(SIZES, TAU, walls=True)
+    for b, (nx, ny) in enumerate(SIZES):
+        setup_member(B[b], b, nx, ny)
+    B.set_body_force(*FB)
+    return B
+
+
+def test_launch_shapes_are_bitwise_identical():
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    ref = None
+    for ty in (1, 2, 4, 8):
+        for g in (0, 2, 8):
+            lat = Lattice(67, 37, 0.7, walls=True)
+            lat.set_launch_shape(ty, g)
+            f = workloads.random_fields(67, 37, seed=4)
+            lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+            lat.add_disks([(20.0, 15.0, 5.0)])
+            lat.set_stirring(2, 5, 1e-4, 9)
+            lat.set_body_force(1e-4, 0)
+            lat.step(11)
+            s = lat.save_state().cpu()
+            if ref is None:
+                ref = s
+            assert torch.equal(s, ref), (ty, g)
+
+
+@pytest.mark.parametrize("graph", [16, 0], ids=["graph", "direct"])
+def test_batch_members_equal_single_runs(graph):
+    torch = need_gpu()
+    steps = 37
+    want = single_runs(steps)
+    B = make_batch()
+    B.use_graph(graph)
+    B.step(steps)
+    B.sync()
+    for b in range(len(SIZES)):
+        f, g = B[b].planes()
+        assert torch.equal(f.cpu(), want[b][0]), b
+        assert torch.equal(g.cpu(), want[b][1]), b
+        assert B[b].step_count == steps
+
+
+def test_graph_replays_with_eager_work_between():
+    torch = need_gpu()
+    want = single_runs(16 * 3 + 5)
+    B = make_batch()
+    B.step(5)                   # direct steps, odd phase
+    for _ in range(3):          # three replays of one 16-step graph
+        B.step(16)
+        B[0].fields(["eps"])     # eager work between replays
+        B[1].conserved()
+    B.sync()
+    for b in range(len(SIZES)):
+        f, g = B[b].planes()
+        assert torch.equal(f.cpu(), want[b][0]), b
+        assert torch.equal(g.cpu(), want[b][1]), b
+
+
+def test_autotune_does_not_advance_and_keeps_results():
+    torch = need_gpu()
+    B = make_batch()
+    B.step(3)
+    before = [B[b].save_state().cpu() for b in range(len(SIZES))]
+    rows = B.autotune(trials=2)
+    assert len(rows) == 16 and all(r[2] > 0 for r in rows)
+    after = [B[b].save_state().cpu() for b in range(len(SIZES))]
+    for x, y in zip(before, after):
+        assert torch.equal(x, y)
+    B.step(34)
+    want = single_runs(37)
+    for b in range(len(SIZES)):
+        f, g = B[b].planes()
+        assert torch.equal(f.cpu(), want[b][0]), b
+
+
+def test_member_cannot_step_alone():
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import RLBError, EINVAL
+    B = make_batch()
+    with pytest.raises(RLBError) as e:
+        B[0].step(1)
+    assert e.value.status == EINVAL
