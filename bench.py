@@ -18,6 +18,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -186,6 +188,48 @@ def run_batch(torch, rlb, workloads, steps, warmup):
     return out
 
 
+def run_adjoint(torch, rlb, workloads):
+    """The gradient workload: 512 x 256 channel, walls, discs of radius 6 at
+    5 % area (seed 7), tau 0.8, F = 1e-6 x_hat + 32 basis modes (7 <= |k| <=
+    9, amplitudes 1e-6); 2000 steps, checkpoint every 100; objective = the
+    time-averaged charge current.  Throughput counts forward + backward
+    node-steps (nodes x N) per second of the whole adjoint run."""
+    c = workloads.ADJOINT
+    nx, ny = c["nx"], c["ny"]
+    modes = workloads.stirring_basis(nx, ny, c["nmodes"], c["kmin"], c["kmax"], c["seed"])
+    amps = [c["mode_amplitude"]] * c["nmodes"]
+    discs = workloads.channel_discs(nx, ny, c["radius"], c["fraction"], c["seed"])
+
+    def fresh():
+        lat = rlb.Lattice(nx, ny, c["tau"], walls=True, eps_ref=c["eps"], n_ref=c["n"])
+        f = workloads.uniform(nx, ny, c["eps"], c["n"])
+        lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        lat.add_disks(discs)
+        return lat
+
+    out = {}
+    for grad in (False, True):
+        lat = fresh()
+        lat.adjoint_run(4, 2, "current", modes, amps, c["body_force"], grad=grad)   # warm
+        lat = fresh()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, g = lat.adjoint_run(c["steps"], c["checkpoint"], "current", modes, amps,
+                               c["body_force"], grad=grad)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out["adjoint" if grad else "forward"] = dict(seconds=wall, mlups=nx * ny * c["steps"] / wall / 1e6)
+        if grad:
+            out["objective"] = J
+            out["grad_norm"] = float(np.linalg.norm(g))
+            out["dJ_dFb"] = float(g[0])
+            out["dJ_dtau"] = float(g[1])
+    out["workload"] = ("adjoint channel 512x256, 5% discs r=6 (seed 7), tau 0.8, body force 1e-6, "
+                       "32 basis modes 7<=|k|<=9 amp 1e-6, N=2000, K=100, objective: mean J^x")
+    out["adjoint_vs_forward"] = out["adjoint"]["mlups"] / out["forward"]["mlups"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +239,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -215,6 +260,10 @@ def main():
     if not a.no_batch:
         batched = run_batch(torch, rlb, workloads, max(a.steps // 5, 50), 20)
         batched["vs_plain"] = batched["mlups"] / main_run["mlups"]
+    adjoint = None
+    if not a.no_adjoint:
+        adjoint = run_adjoint(torch, rlb, workloads)
+        adjoint["vs_plain"] = adjoint["adjoint"]["mlups"] / main_run["mlups"]
     copy_gbs = copy_probe_gbs(torch, rlb)
     cpu = None if a.no_cpu_baseline else cpu_baseline()
     r = main_run
@@ -235,6 +284,7 @@ def main():
                      "bytes_per_cell": r["bytes_per_cell"], "bytes_per_launch": r["bytes_per_launch"]},
         "copy_probe_gbs": copy_gbs,
         "batched": batched,
+        "adjoint": adjoint,
         "variants": variants,
         "cpu_baseline": cpu,
     }

@@ -58,7 +58,8 @@ typedef enum {
                           /* the 17 z-mirror-folded planes (see rlb_create)   */
 
 /* Lattice parameters.
- *   nx, ny   lattice nodes (one z node); 4 <= nx, ny; nx*ny < 2^31.
+ *   nx, ny   lattice nodes (one z node); 4 <= nx, ny; ny * (nx rounded up
+ *            to 64) < 2^30.
  *   tau      relaxation time in time steps, tau > 1/2 (Ch. 3: eta =
  *            tau_R (eps + P) / 5; the scheme's shear viscosity is
  *            (tau - 1/2)/5 + nu_interp).
@@ -176,10 +177,12 @@ rlb_status rlb_state_bytes(const rlb_lattice* lat, size_t* bytes);
 rlb_status rlb_save_state(rlb_lattice* lat, void* d_buf, size_t bytes);
 rlb_status rlb_load_state(rlb_lattice* lat, const void* d_buf, size_t bytes);
 
-/* Number of population planes per family (17 or 26) and the plane pitch in
- * elements used in saved states (planes start at header + k * pitch * 4). */
-rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int64_t* pitch,
-                      size_t* header_bytes);
+/* Layout of the population planes in saved states: `planes` per family (17
+ * or 26), each plane [ny][row_pitch] float32 (row_pitch = nx rounded up to
+ * 64, so every row starts on a 256-byte boundary; columns nx.. are unused),
+ * plane k at byte header_bytes + 4 * k * pitch.  F planes come first. */
+rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitch,
+                      int64_t* pitch, size_t* header_bytes);
 
 /* Stirring coefficients of a given step without advancing anything:
  * d_out[4m .. 4m+3] = (Re Fx_hat, Im Fx_hat, Re Fy_hat, Im Fy_hat) of mode
@@ -278,6 +281,45 @@ rlb_status rlb_batch_use_graph(rlb_batch* batch, int32_t steps_per_graph);
  * (each call synchronises while timing is on). */
 rlb_status rlb_batch_timing(rlb_batch* batch, int32_t enable);
 rlb_status rlb_batch_timing_read(rlb_batch* batch, double* total_ms, int64_t* steps);
+
+/* ------------------------------------------------------------------------
+ * Adjoint: gradients of a time-averaged objective of a driven run with
+ * respect to theta = (F_b, tau, A_1..A_M), by the discrete adjoint of the
+ * step with checkpoint-and-recompute.  The driving force is
+ *   F(x) = F_b x_hat + sum_m A_m e_m cos(2 pi (kx x / nx + ky y / ny) + phase_m)
+ * (a fixed stirring basis; Ch. 4 eq. forceTerm).  Objectives, averaged over
+ * steps N/2 + 1 .. N and over fluid nodes, from the fields of each step
+ * (post-stream moments): RLB_OBJ_CURRENT the charge current J^x;
+ * RLB_OBJ_DISSIPATION pi^{kl} pi^{kl} with pi = T^{kl} - T_eq^{kl}(eps, u)
+ * (k, l over x, y, z), a viscous-dissipation proxy.
+ * ------------------------------------------------------------------------ */
+enum { RLB_OBJ_CURRENT = 0, RLB_OBJ_DISSIPATION = 1 };
+
+typedef struct {
+  int64_t nsteps;          /* N: even, >= 2                                   */
+  int32_t checkpoint;      /* K: states kept every K steps, >= 1               */
+  int32_t objective;       /* RLB_OBJ_*                                        */
+  int32_t nmodes;          /* M basis modes, 0..64                             */
+  const double* h_modes;   /* host [M][5]: kx, ky (integers), ex, ey, phase    */
+  const double* h_amps;    /* host [M]: amplitudes A_m                          */
+  double body_force;       /* F_b                                              */
+} rlb_adjoint_cfg;
+
+/* Set the relaxation time (tau > 1/2) of an existing lattice. */
+rlb_status rlb_set_relaxation_time(rlb_lattice* lat, double tau);
+
+/* Bytes of the adjoint workspace: ceil(N/K) checkpoints + K segment states
+ * + 2 adjoint states + float64 per-node accumulators. */
+rlb_status rlb_adjoint_workspace_bytes(const rlb_lattice* lat, const rlb_adjoint_cfg* cfg,
+                                       size_t* bytes);
+
+/* Run N steps from the lattice's current state with the force above
+ * (overwriting the lattice's stirring-force planes), write J to
+ * *h_objective and, if h_grad is not null, the gradient (2 + M doubles:
+ * dJ/dF_b, dJ/dtau, dJ/dA_m) computed by the adjoint.  The lattice is left
+ * at step N.  Synchronises.  d_ws: 256-byte aligned device memory. */
+rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d_ws,
+                           size_t bytes, double* h_objective, double* h_grad);
 
 /* A plain device copy of `bytes` (multiple of 16) for bandwidth calibration. */
 rlb_status rlb_copy_probe(const void* d_src, void* d_dst, size_t bytes,

@@ -1,0 +1,271 @@
+// Adjoint run: forward with checkpoints every K steps, then segments in
+// reverse order -- restore the checkpoint, recompute and store the K states
+// of the segment, sweep the adjoint kernel back through them -- and reduce
+// the per-node parameter adjoints to dJ/d(F_b, tau, A_1..A_M).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace rlb;
+
+namespace {
+
+constexpr int kObjBlocks = 512;
+constexpr int kGradCols = 256;
+constexpr int kMaxModesAdj = 64;
+
+rlb_status afail(rlb_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  set_error_message(buf);
+  return s;
+}
+
+#define AHIP(expr, what)                                                                \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) return afail(RLB_EDEVICE, "%s: %s", what, hipGetErrorString(_e)); \
+  } while (0)
+
+struct AdjLayout {
+  size_t state_bytes, ck_off, store_off, mu_off, accf_off, acct_off, obj_off, modes_off,
+      partial_off, result_off, desc_off, total;
+  int64_t nseg;
+};
+
+rlb_status check_cfg(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
+  if (!lat) return afail(RLB_EINVAL, "lattice is null");
+  if (!c) return afail(RLB_EINVAL, "config is null");
+  if (c->nsteps < 2 || (c->nsteps & 1)) return afail(RLB_EINVAL, "nsteps must be even and >= 2");
+  if (c->checkpoint < 1) return afail(RLB_EINVAL, "checkpoint interval must be >= 1");
+  if (c->objective != RLB_OBJ_CURRENT && c->objective != RLB_OBJ_DISSIPATION)
+    return afail(RLB_EINVAL, "unknown objective %d", c->objective);
+  if (c->nmodes < 0 || c->nmodes > kMaxModesAdj) return afail(RLB_EINVAL, "nmodes must be in [0, 64]");
+  if (c->nmodes > 0 && (!c->h_modes || !c->h_amps)) return afail(RLB_EINVAL, "mode arrays are null");
+  if (!std::isfinite(c->body_force)) return afail(RLB_EINVAL, "body force must be finite");
+  for (int m = 0; m < c->nmodes; ++m) {
+    for (int k = 0; k < 5; ++k)
+      if (!std::isfinite(c->h_modes[5 * m + k])) return afail(RLB_EINVAL, "mode %d is not finite", m);
+    if (!std::isfinite(c->h_amps[m])) return afail(RLB_EINVAL, "amplitude %d is not finite", m);
+    if (c->h_modes[5 * m] != std::floor(c->h_modes[5 * m]) ||
+        c->h_modes[5 * m + 1] != std::floor(c->h_modes[5 * m + 1]))
+      return afail(RLB_EINVAL, "mode %d wave numbers must be integers", m);
+  }
+  return RLB_OK;
+}
+
+AdjLayout adj_layout(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
+  AdjLayout L;
+  const size_t ncell = (size_t)lat->p.nx * lat->p.ny;
+  L.state_bytes = align_up((size_t)2 * lat->Q * lat->pitch * sizeof(float));
+  L.nseg = (c->nsteps + c->checkpoint - 1) / c->checkpoint;
+  const int64_t K = std::min<int64_t>(c->checkpoint, c->nsteps);
+  size_t off = 0;
+  L.ck_off = off; off += L.state_bytes * (size_t)L.nseg;
+  L.store_off = off; off += L.state_bytes * (size_t)K;
+  L.mu_off = off; off += 2 * L.state_bytes;
+  L.accf_off = off; off += align_up(ncell * sizeof(double2));
+  L.acct_off = off; off += align_up(ncell * sizeof(double));
+  L.obj_off = off; off += align_up(2 * kObjBlocks * sizeof(double));
+  L.modes_off = off; off += align_up(kMaxModesAdj * 6 * sizeof(double));
+  L.partial_off = off; off += align_up((size_t)(2 + kMaxModesAdj) * kGradCols * sizeof(double));
+  L.result_off = off; off += align_up(128 * sizeof(double));
+  L.desc_off = off; off += align_up(sizeof(LatDesc) * (size_t)K);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+rlb_status rlb_set_relaxation_time(rlb_lattice* lat, double tau) {
+  if (!lat) return afail(RLB_EINVAL, "lattice is null");
+  if (!std::isfinite(tau) || !(tau > 0.5)) return afail(RLB_EINVAL, "tau must be finite and > 1/2");
+  lat->p.tau = tau;
+  return RLB_OK;
+}
+
+rlb_status rlb_adjoint_workspace_bytes(const rlb_lattice* lat, const rlb_adjoint_cfg* cfg,
+                                       size_t* bytes) {
+  if (rlb_status s = check_cfg(lat, cfg)) return s;
+  if (!bytes) return afail(RLB_EINVAL, "bytes is null");
+  *bytes = adj_layout(lat, cfg).total;
+  return RLB_OK;
+}
+
+rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d_ws, size_t bytes,
+                           double* h_objective, double* h_grad) {
+  if (rlb_status s = check_cfg(lat, cfg)) return s;
+  if (lat->owner) return afail(RLB_EINVAL, "lattice is a batch member");
+  const AdjLayout L = adj_layout(lat, cfg);
+  if (!d_ws || ((uintptr_t)d_ws % kAlign)) return afail(RLB_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < L.total) return afail(RLB_ENOMEM, "adjoint workspace has %zu bytes, needs %zu", bytes, L.total);
+  if (!h_objective) return afail(RLB_EINVAL, "objective output is null");
+  char* ws = (char*)d_ws;
+  hipStream_t st = lat->stream;
+  const int nx = lat->p.nx, ny = lat->p.ny, M = cfg->nmodes;
+  const int64_t N = cfg->nsteps, K = std::min<int64_t>(cfg->checkpoint, N);
+  const size_t SB = L.state_bytes;
+  const size_t state_copy = (size_t)2 * lat->Q * lat->pitch * sizeof(float);
+  auto ck = [&](int64_t k) { return (float*)(ws + L.ck_off + SB * k); };
+  auto store = [&](int64_t j) { return (float*)(ws + L.store_off + SB * j); };
+  float* mu[2] = {(float*)(ws + L.mu_off), (float*)(ws + L.mu_off + SB)};
+  double2* acc_f = (double2*)(ws + L.accf_off);
+  double* acc_t = (double*)(ws + L.acct_off);
+  double* obj = (double*)(ws + L.obj_off);
+  double* d_modes = (double*)(ws + L.modes_off);
+  double* partial = (double*)(ws + L.partial_off);
+  double* result = (double*)(ws + L.result_off);
+  LatDesc* d_desc = (LatDesc*)(ws + L.desc_off);
+
+  // static force: F_b along x (uniform) + sum_m A_m phi_m (force planes)
+  std::vector<double> host(6 * kMaxModesAdj, 0.0);
+  for (int m = 0; m < M; ++m) {
+    for (int k = 0; k < 5; ++k) host[5 * m + k] = cfg->h_modes[5 * m + k];
+    host[5 * kMaxModesAdj + m] = cfg->h_amps[m];
+  }
+  AHIP(hipMemcpyAsync(d_modes, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, st),
+       "upload modes");
+  AHIP(hipStreamSynchronize(st), "stream synchronize");
+  AHIP(launch_basis_force(d_modes, d_modes + 5 * kMaxModesAdj, M, nx, ny, lat->row, lat->pitch,
+                          (float*)lat->desc.force, st), "basis force");
+  const double saved_fx = lat->fx, saved_fy = lat->fy;
+  lat->fx = cfg->body_force;
+  lat->fy = 0.0;
+  StepShared sh = shared_of(lat);
+  const bool unit = lat->p.cfl == 1.0, mask = lat->any_solid;
+
+  // recompute descriptors: store[j] -> store[j + 1]
+  std::vector<LatDesc> hd((size_t)K);
+  for (int64_t j = 0; j < K; ++j) {
+    LatDesc d = lat->desc;
+    d.state[0] = store(j);
+    d.state[1] = store(std::min<int64_t>(j + 1, K - 1));
+    hd[j] = d;
+  }
+  AHIP(hipMemcpyAsync(d_desc, hd.data(), sizeof(LatDesc) * K, hipMemcpyHostToDevice, st), "descriptors");
+  AHIP(hipStreamSynchronize(st), "stream synchronize");
+
+  ObjArgs oa;
+  oa.sh = sh;
+  oa.mask = mask ? lat->mask : nullptr;
+  oa.pitch = lat->pitch;
+  oa.nx = nx;
+  oa.ny = ny;
+  oa.row = lat->row;
+  AHIP(launch_zero_f64(obj, 2 * kObjBlocks, st), "zero objective");
+  // fluid node count
+  oa.state = lat->state[lat->cur];
+  oa.acc = obj + kObjBlocks;
+  oa.kind = 2;
+  AHIP(launch_objective(lat->Q, unit, mask, oa, kObjBlocks, st), "count fluid");
+  AHIP(launch_sum_rows(obj + kObjBlocks, kObjBlocks, 1, 1.0, result + 64, st), "sum");
+  double nfluid = 0.0;
+  AHIP(hipMemcpyAsync(&nfluid, result + 64, sizeof(double), hipMemcpyDeviceToHost, st), "read count");
+  AHIP(hipStreamSynchronize(st), "stream synchronize");
+  if (!(nfluid > 0.0)) {
+    lat->fx = saved_fx;
+    lat->fy = saved_fy;
+    return afail(RLB_EINVAL, "the lattice has no fluid node");
+  }
+  const double cw = 1.0 / ((double)(N - N / 2) * nfluid);
+  oa.kind = cfg->objective;
+  oa.acc = obj;
+
+  // ---- forward with checkpoints ----
+  for (int64_t t = 0; t < N; ++t) {
+    if (t % K == 0)
+      AHIP(hipMemcpyAsync(ck(t / K), lat->state[lat->cur], state_copy, hipMemcpyDeviceToDevice, st),
+           "checkpoint");
+    AHIP(launch_step(lat, MODE_STEP, FORCE_STIR, lat->cur, nullptr, 0), "step");
+    lat->cur ^= 1;
+    lat->step += 1;
+    if (t + 1 > N / 2) {
+      oa.state = lat->state[lat->cur];
+      AHIP(launch_objective(lat->Q, unit, mask, oa, kObjBlocks, st), "objective");
+    }
+  }
+  AHIP(launch_sum_rows(obj, kObjBlocks, 1, cw, result, st), "objective sum");
+  double J = 0.0;
+  AHIP(hipMemcpyAsync(&J, result, sizeof(double), hipMemcpyDeviceToHost, st), "read objective");
+  AHIP(hipStreamSynchronize(st), "stream synchronize");
+  *h_objective = J;
+
+  if (h_grad) {
+    // ---- backward ----
+    const size_t ncell = (size_t)nx * ny;
+    AHIP(launch_zero_f64((double*)acc_f, 2 * ncell, st), "zero");
+    AHIP(launch_zero_f64(acc_t, ncell, st), "zero");
+    AdjArgs aa;
+    aa.sh = sh;
+    aa.mask = mask ? lat->mask : nullptr;
+    aa.force = lat->desc.force;
+    aa.acc_f = acc_f;
+    aa.acc_itau = acc_t;
+    aa.pitch = lat->pitch;
+    aa.nx = nx;
+    aa.ny = ny;
+    aa.row = lat->row;
+    aa.tiles_x = (nx + 63) / 64;
+    aa.ntiles = aa.tiles_x * ((ny + 3) / 4);
+    aa.kind = cfg->objective;
+    int cm = 0;
+    // t = N: mu_N = dJ_N / dF~ only
+    aa.state = lat->state[lat->cur];
+    aa.mu_in = nullptr;
+    aa.mu_out = mu[cm];
+    aa.obj_c = (float)cw;
+    AHIP(launch_adjoint(lat->Q, unit, mask, aa, st), "adjoint");
+    TileArgs ta;
+    ta.sh = sh;
+    ta.tile_lat = nullptr;
+    ta.parity = 0;
+    ta.tile_first = 0;
+    ta.ntiles = tiles_of(nx, ny, lat->Q == 17 ? lat->shape.tile_rows : 4);
+    ta.fields = nullptr;
+    for (int64_t seg = L.nseg - 1; seg >= 0; --seg) {
+      const int64_t t0 = seg * K, len = std::min<int64_t>(K, N - t0);
+      AHIP(hipMemcpyAsync(store(0), ck(seg), state_copy, hipMemcpyDeviceToDevice, st), "restore");
+      for (int64_t j = 0; j + 1 < len; ++j) {
+        ta.lats = d_desc + j;
+        AHIP(launch_tiles(lat->Q, unit, mask, MODE_STEP, FORCE_STIR, ta, lat->shape, lat->num_cu, st),
+             "recompute");
+      }
+      for (int64_t t = t0 + len - 1; t >= t0; --t) {
+        aa.state = store(t - t0);
+        aa.mu_in = mu[cm];
+        aa.mu_out = mu[cm ^ 1];
+        aa.obj_c = t > N / 2 ? (float)cw : 0.0f;
+        AHIP(launch_adjoint(lat->Q, unit, mask, aa, st), "adjoint");
+        cm ^= 1;
+      }
+    }
+    AHIP(launch_grad_reduce(acc_f, acc_t, d_modes, M, nx, ny, lat->p.tau, partial, kGradCols,
+                            result + 1, st), "gradient reduce");
+    std::vector<double> g((size_t)(2 + M));
+    AHIP(hipMemcpyAsync(g.data(), result + 1, sizeof(double) * (2 + M), hipMemcpyDeviceToHost, st),
+         "read gradient");
+    AHIP(hipStreamSynchronize(st), "stream synchronize");
+    std::memcpy(h_grad, g.data(), sizeof(double) * (2 + M));
+  }
+  lat->fx = saved_fx;
+  lat->fy = saved_fy;
+  uint32_t h = 0;
+  AHIP(hipMemcpyAsync(&h, lat->err, sizeof h, hipMemcpyDeviceToHost, st), "read error flag");
+  AHIP(hipStreamSynchronize(st), "stream synchronize");
+  if (h & ERR_LANDAU) return afail(RLB_ELANDAU, "a fluid node had no timelike Landau frame");
+  return RLB_OK;
+}
+
+}  // extern "C"

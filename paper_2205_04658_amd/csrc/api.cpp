@@ -56,8 +56,8 @@ struct StateHeader {
 rlb_status check_params(const rlb_params* p) {
   if (!p) return fail(RLB_EINVAL, "params is null");
   if (p->nx < 4 || p->ny < 4) return fail(RLB_EINVAL, "nx, ny must be >= 4 (got %d x %d)", p->nx, p->ny);
-  if ((int64_t)p->nx * p->ny >= (int64_t)1 << 31)
-    return fail(RLB_EINVAL, "nx * ny must be < 2^31");
+  if ((int64_t)p->ny * (((int64_t)p->nx + 63) / 64 * 64) >= (int64_t)1 << 30)
+    return fail(RLB_EINVAL, "ny * (nx rounded up to 64) must be < 2^30");
   if (!std::isfinite(p->tau) || !(p->tau > 0.5)) return fail(RLB_EINVAL, "tau must be finite and > 1/2");
   if (!std::isfinite(p->cfl) || !(p->cfl > 0.0) || p->cfl > 1.0)
     return fail(p->cfl > 1.0 && std::isfinite(p->cfl) ? RLB_EUNSUPPORTED : RLB_EINVAL,
@@ -81,6 +81,7 @@ Workspace layout(const rlb_params* p, int Q, int64_t pitch) {
   w.table_off = off; off += align_up((size_t)p->ny * (kMaxK + 1) * sizeof(float4));
   w.phase_off = off; off += align_up((size_t)p->ny * sizeof(double2));
   w.force_off = off; off += align_up((size_t)2 * pitch * sizeof(float));
+  w.twiddle_off = off; off += align_up((size_t)kMaxK * p->nx * sizeof(float2));
   w.partial_off = off; off += align_up((size_t)kRedBlocks * 4 * sizeof(double));
   w.desc_off = off; off += align_up(sizeof(LatDesc));
   w.misc_off = off; off += align_up(256);
@@ -122,8 +123,10 @@ StirArgs stir_args(const rlb_lattice* lat) {
   a.coef = lat->coef;
   a.table = lat->table;
   a.phase = lat->phase;
+  a.twiddle = lat->twiddle;
   a.force = lat->force;
   a.force_pitch = lat->pitch;
+  a.row = lat->row;
   a.dstep = lat->dstep;
   a.nmodes = lat->nmodes;
   a.K = lat->K;
@@ -179,7 +182,7 @@ rlb_status rlb_workspace_bytes(const rlb_params* p, size_t* bytes) {
   if (s) return s;
   if (!bytes) return fail(RLB_EINVAL, "bytes is null");
   const int Q = planes_of(p);
-  const int64_t pitch = (int64_t)align_up((size_t)p->nx * p->ny, 64);
+  const int64_t pitch = (int64_t)align_up((size_t)p->ny * align_up((size_t)p->nx, 64), 64);
   *bytes = layout(p, Q, pitch).total;
   return RLB_OK;
 }
@@ -193,7 +196,8 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   if (!d_workspace || !aligned(d_workspace, kAlign))
     return fail(RLB_EINVAL, "workspace must be a non-null 256-byte aligned device pointer");
   const int Q = planes_of(p);
-  const int64_t pitch = (int64_t)align_up((size_t)p->nx * p->ny, 64);
+  const int row = (int)align_up((size_t)p->nx, 64);
+  const int64_t pitch = (int64_t)align_up((size_t)p->ny * row, 64);
   const Workspace w = layout(p, Q, pitch);
   if (bytes < w.total) return fail(RLB_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, w.total);
   int dev = -1;
@@ -215,6 +219,7 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   lat->device = dev;
   lat->stream = (hipStream_t)hip_stream;
   lat->Q = Q;
+  lat->row = row;
   lat->pitch = pitch;
   lat->ws = (char*)d_workspace;
   lat->ws_bytes = bytes;
@@ -229,6 +234,7 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   lat->table = (float4*)(lat->ws + w.table_off);
   lat->phase = (double2*)(lat->ws + w.phase_off);
   lat->force = (float*)(lat->ws + w.force_off);
+  lat->twiddle = (float2*)(lat->ws + w.twiddle_off);
   lat->partials = (double*)(lat->ws + w.partial_off);
   lat->err = (uint32_t*)(lat->ws + w.misc_off);
   lat->dstep = (int64_t*)(lat->ws + w.misc_off + 64);
@@ -245,11 +251,18 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   lat->desc.ny = p->ny;
   lat->desc.tiles_x = (p->nx + 63) / 64;
   lat->desc.tile_begin = 0;
+  lat->desc.row = row;
+  lat->desc.pad = 0;
   lat->result = (double*)(lat->ws + w.misc_off + 128);
   if (Q == 17) fill_taps<Dir17>(lat); else fill_taps<Dir26>(lat);
 
   rlb_status st = RLB_OK;
-  e = launch_fill_u8(lat->mask, (size_t)p->nx * p->ny, 0, lat->stream);
+  // zero both state copies and the force planes: the row padding is never
+  // written by the kernels, so saved states are then byte-deterministic
+  e = launch_fill_u8((uint8_t*)lat->state[0], 2 * (w.state_off[1] - w.state_off[0]), 0, lat->stream);
+  if (e == hipSuccess)
+    e = launch_fill_u8((uint8_t*)(lat->ws + w.force_off), (size_t)2 * pitch * sizeof(float), 0, lat->stream);
+  if (e == hipSuccess) e = launch_fill_u8(lat->mask, (size_t)p->nx * p->ny, 0, lat->stream);
   if (e == hipSuccess) e = launch_fill_u8((uint8_t*)lat->err, 64, 0, lat->stream);
   if (e == hipSuccess) e = launch_set_i64(lat->dstep, 0, lat->stream);
   if (e == hipSuccess) e = launch_phase(lat);
@@ -391,6 +404,7 @@ rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax, double a
   lat->seed = seed;
   lat->nmodes = (int)modes.size();
   lat->K = kmaxx;
+  HIP_TRY(launch_twiddle(lat->twiddle, kmaxx, lat->p.nx, lat->stream), "twiddle table");
   HIP_TRY(launch_set_i64(lat->dstep, lat->step, lat->stream), "step counter");
   return RLB_OK;
 }
@@ -463,9 +477,11 @@ rlb_status rlb_state_bytes(const rlb_lattice* lat, size_t* bytes) {
   return RLB_OK;
 }
 
-rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int64_t* pitch, size_t* header_bytes) {
+rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitch, int64_t* pitch,
+                      size_t* header_bytes) {
   if (rlb_status s = check_lat(lat)) return s;
   if (planes) *planes = lat->Q;
+  if (row_pitch) *row_pitch = lat->row;
   if (pitch) *pitch = lat->pitch;
   if (header_bytes) *header_bytes = kHeaderBytes;
   return RLB_OK;
@@ -547,8 +563,9 @@ rlb_status rlb_stirring_field(rlb_lattice* lat, int64_t step, float* d_out) {
   HIP_TRY(launch_stir_synth(a, lat->stream), "stirring synthesis");
   const size_t plane = (size_t)lat->p.nx * lat->p.ny;
   for (int c = 0; c < 2; ++c)
-    HIP_TRY(hipMemcpyAsync(d_out + c * plane, lat->force + c * lat->pitch, plane * sizeof(float),
-                           hipMemcpyDeviceToDevice, lat->stream), "copy force");
+    HIP_TRY(hipMemcpy2DAsync(d_out + c * plane, sizeof(float) * lat->p.nx, lat->force + c * lat->pitch,
+                             sizeof(float) * lat->row, sizeof(float) * lat->p.nx, lat->p.ny,
+                             hipMemcpyDeviceToDevice, lat->stream), "copy force");
   return RLB_OK;
 }
 

@@ -9,8 +9,8 @@
 // a_k cos(k th) + b_k sin(k th), th = 2 pi x / nx, summing modes in a fixed
 // order; (3) the synthesis kernel evaluates the series at every node and
 // writes the two force planes the step kernel reads.  Each synthesis thread
-// owns one column, computes its cos/sin(k th) once (exactly reduced
-// sincospi) and sweeps 64 rows, so the per-node cost is 4 FMAs per k.
+// owns one column, loads its cos/sin(k th) once from a static twiddle table
+// and sweeps 32 rows, so the per-node cost is 4 FMAs per k.
 #include "internal.hpp"
 #include "device_common.hpp"
 
@@ -70,24 +70,36 @@ __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a) {
   a.table[(size_t)y * kTableStride + k] = out;
 }
 
-constexpr int kSynthRows = 64;
+constexpr int kSynthRows = 32;
+
+// Column twiddles (cos, sin)(2 pi k x / nx), k = 1..K, table [K][nx],
+// exactly reduced; static per lattice and shell.
+__global__ __launch_bounds__(256) void twiddle_kernel(float2* tw, int K, int nx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K * nx) return;
+  const int k = i / nx + 1, x = i - (k - 1) * nx;
+  double sn, cs;
+  sincospi(2.0 * (double)(((long long)k * x) % nx) / (double)nx, &sn, &cs);
+  tw[i] = make_float2((float)cs, (float)sn);
+}
 
 template <int KB>
 __global__ __launch_bounds__(64) void stir_synth_kernel(const float4* __restrict__ table,
+                                                        const float2* __restrict__ tw,
                                                         float* __restrict__ force,
                                                         int64_t force_pitch, int K,
-                                                        int nx, int ny) {
+                                                        int nx, int ny, int row_pitch) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y0 = blockIdx.y * kSynthRows;
-  const float ts = 2.0f / (float)nx;
+  if (x >= nx) return;
   float c[KB], s[KB];
 #pragma unroll
   for (int k = 1; k <= KB; ++k) {
-    c[k - 1] = 0.0f;
-    s[k - 1] = 0.0f;
-    if (k <= K) sincospif((float)((k * x) % nx) * ts, &s[k - 1], &c[k - 1]);
+    float2 t = make_float2(0.0f, 0.0f);
+    if (k <= K) t = tw[(size_t)(k - 1) * nx + x];
+    c[k - 1] = t.x;
+    s[k - 1] = t.y;
   }
-  if (x >= nx) return;
   const int y1 = min(y0 + kSynthRows, ny);
   for (int y = y0; y < y1; ++y) {
     // the row's coefficients are wave-uniform: scalar loads
@@ -100,8 +112,8 @@ __global__ __launch_bounds__(64) void stir_synth_kernel(const float4* __restrict
       fx += t.x * c[k - 1] + t.y * s[k - 1];
       fy += t.z * c[k - 1] + t.w * s[k - 1];
     }
-    force[(size_t)y * nx + x] = fx;
-    force[force_pitch + (size_t)y * nx + x] = fy;
+    force[(size_t)y * row_pitch + x] = fx;
+    force[force_pitch + (size_t)y * row_pitch + x] = fy;
   }
 }
 
@@ -144,8 +156,8 @@ hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s) {
   const dim3 grid((a.nx + 63) / 64, (a.ny + kSynthRows - 1) / kSynthRows);
   const float4* t = a.table;
 #define RLB_SYNTH(KB)                                                                  \
-  hipLaunchKernelGGL(stir_synth_kernel<KB>, grid, dim3(64), 0, s, t, a.force, a.force_pitch, \
-                     a.K, a.nx, a.ny)
+  hipLaunchKernelGGL(stir_synth_kernel<KB>, grid, dim3(64), 0, s, t, a.twiddle, a.force,     \
+                     a.force_pitch, a.K, a.nx, a.ny, a.row)
   if (a.K <= 8) RLB_SYNTH(8);
   else if (a.K <= 16) RLB_SYNTH(16);
   else if (a.K <= 24) RLB_SYNTH(24);
@@ -153,6 +165,12 @@ hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s) {
   else if (a.K <= 48) RLB_SYNTH(48);
   else RLB_SYNTH(63);
 #undef RLB_SYNTH
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddle(float2* tw, int K, int nx, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(twiddle_kernel, dim3((K * nx + 255) / 256), dim3(256), 0, s, tw, K, nx);
   return hipGetLastError();
 }
 

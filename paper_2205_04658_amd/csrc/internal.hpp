@@ -50,7 +50,8 @@ struct LatDesc {
   int32_t nx, ny;
   int32_t tiles_x;        // tiles per row of tiles
   int32_t tile_begin;     // first global tile index of this lattice
-  int32_t pad[2];
+  int32_t row;            // row pitch in elements (nx rounded up to 64)
+  int32_t pad;
 };
 
 struct TileArgs {
@@ -78,17 +79,44 @@ struct StirArgs {
   double* coef;           // [nmodes][4] (Re Fx, Im Fx, Re Fy, Im Fy)
   float4* table;          // [ny][kMaxK+1]
   const double2* phase;   // [ny] (cos, sin)(2 pi m / ny)
-  float* force;           // [2][force_pitch] synthesised force planes
+  const float2* twiddle;  // [K][nx] (cos, sin)(2 pi k x / nx)
+  float* force;           // [2][force_pitch] synthesised force planes, rows padded
   int64_t force_pitch;
+  int32_t row;
   int64_t* dstep;         // device step counter (draw reads and advances it)
   int32_t nmodes, K, nx, ny;
   double amplitude;
   uint64_t seed, stream;
 };
 
+// Adjoint kernels (adjoint.hip).
+struct AdjArgs {
+  StepShared sh;
+  const float* state;     // s_t planes [2Q][pitch]
+  const float* mu_in;     // mu_{t+1} (null: zero)
+  float* mu_out;          // mu_t
+  const uint8_t* mask;    // solid flags [ny][nx] or null
+  const float* force;     // static stirring-basis planes [2][pitch]
+  double2* acc_f;         // per-node sum of dJ/dF(x), dense [ny][nx]
+  double* acc_itau;       // per-node sum of dJ/d(1/tau)
+  int64_t pitch;
+  int32_t nx, ny, row, tiles_x, ntiles;
+  float obj_c;            // weight of J_t (0 outside the averaging window)
+  int32_t kind;           // 0 current, 1 dissipation
+};
+
+struct ObjArgs {
+  StepShared sh;
+  const float* state;
+  const uint8_t* mask;
+  double* acc;            // per-block running sums [grid]
+  int64_t pitch;
+  int32_t nx, ny, row, kind;   // kind 2 counts fluid nodes
+};
+
 struct Workspace {
   size_t state_off[2], mask_off, coef_off, modes_off, bins_off, table_off,
-      phase_off, force_off, partial_off, desc_off, misc_off, total;
+      phase_off, force_off, twiddle_off, partial_off, desc_off, misc_off, total;
 };
 
 }  // namespace rlb
@@ -103,7 +131,8 @@ struct rlb_lattice {
   int device;
   hipStream_t stream;
   int Q;                  // planes per family (17 or 26)
-  int64_t pitch;
+  int32_t row;            // row pitch in elements (nx rounded up to 64)
+  int64_t pitch;          // plane pitch in elements (ny * row rounded up)
   char* ws;
   size_t ws_bytes;
   rlb::Workspace lay;
@@ -116,6 +145,7 @@ struct rlb_lattice {
   int32_t* bins;
   float4* table;
   double2* phase;
+  float2* twiddle;
   float* force;
   double* partials;
   uint32_t* err;
@@ -168,9 +198,22 @@ hipError_t launch_stir_draw(const StirArgs& a, int64_t fixed_step,
 hipError_t launch_stir_table(const StirArgs& a, hipStream_t s);
 hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s);
 hipError_t launch_phase(const rlb_lattice* lat);
+hipError_t launch_twiddle(float2* tw, int K, int nx, hipStream_t s);
 hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count,
                          uint64_t* out, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+
+// adjoint.hip
+hipError_t launch_adjoint(int Q, bool unit, bool mask, const AdjArgs& a, hipStream_t s);
+hipError_t launch_objective(int Q, bool unit, bool mask, const ObjArgs& a, int grid, hipStream_t s);
+hipError_t launch_basis_force(const double* modes, const double* amps, int M, int nx, int ny,
+                              int row, int64_t pitch, float* force, hipStream_t s);
+hipError_t launch_grad_reduce(const double2* acc_f, const double* acc_itau, const double* modes,
+                              int M, int nx, int ny, double tau, double* partial, int cols,
+                              double* out, hipStream_t s);
+hipError_t launch_sum_rows(const double* partial, int cols, int rows, double scale, double* out,
+                           hipStream_t s);
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s);
 
 // reduce.hip
 hipError_t launch_totals(const rlb_lattice* lat, const float* state,

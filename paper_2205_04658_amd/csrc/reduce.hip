@@ -18,12 +18,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 template <class DS>
 __global__ __launch_bounds__(256) void totals_kernel(const float* __restrict__ st,
-                                                     int64_t pitch, int ncell,
+                                                     int64_t pitch, int nx, int ny, int row,
                                                      double* partial) {
   constexpr int Q = DS::Q;
   double e = 0.0, px = 0.0, py = 0.0, q = 0.0;
   const int stride = gridDim.x * blockDim.x;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += stride) {
+  const int ncell = nx * ny;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ncell; j += stride) {
+    const int yy = j / nx;
+    const int i = yy * row + (j - yy * nx);   // padded offset
     static_for<0, Q>([&](auto P) {
       constexpr int p = decltype(P)::value;
       const double f = (double)st[p * pitch + i];
@@ -86,10 +89,12 @@ hipError_t launch_totals(const rlb_lattice* lat, const float* state,
   const int ncell = lat->p.nx * lat->p.ny;
   if (lat->Q == 17)
     hipLaunchKernelGGL(totals_kernel<Dir17>, dim3(kRedBlocks), dim3(256), 0,
-                       lat->stream, state, lat->pitch, ncell, lat->partials);
+                       lat->stream, state, lat->pitch, lat->p.nx, lat->p.ny, lat->row,
+                       lat->partials);
   else
     hipLaunchKernelGGL(totals_kernel<Dir26>, dim3(kRedBlocks), dim3(256), 0,
-                       lat->stream, state, lat->pitch, ncell, lat->partials);
+                       lat->stream, state, lat->pitch, lat->p.nx, lat->p.ny, lat->row,
+                       lat->partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, lat->stream,

@@ -82,12 +82,13 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
   const int xp = x == nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? ny - 1 : y - 1;
   const int yp = y == ny - 1 ? 0 : y + 1;
-  const uint32_t r0 = (uint32_t)(y * nx), rm = (uint32_t)(ym * nx), rp = (uint32_t)(yp * nx);
+  const int row = L.row;   // row pitch: rows start on 256-byte boundaries
+  const uint32_t r0 = (uint32_t)(y * row), rm = (uint32_t)(ym * row), rp = (uint32_t)(yp * row);
   Nbr nb;
   nb.c0 = 4u * (r0 + x);   nb.cxm = 4u * (r0 + xm); nb.cxp = 4u * (r0 + xp);
   nb.ym0 = 4u * (rm + x);  nb.ymxm = 4u * (rm + xm); nb.ymxp = 4u * (rm + xp);
   nb.yp0 = 4u * (rp + x);  nb.ypxm = 4u * (rp + xm); nb.ypxp = 4u * (rp + xp);
-  const uint32_t node = r0 + (uint32_t)x;
+  const uint32_t node = (uint32_t)(y * nx + x);   // dense index (mask, fields)
   const StepShared& a = sh;
 
   // 1. pull-stream every plane
@@ -98,19 +99,16 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
     g[p] = pull<DS, UNIT, p>(src + (Q + p) * pitch, a, nb);
   });
 
+  float Fsx = 0.0f, Fsy = 0.0f;   // stirring force, loaded with the populations
+  if constexpr (FORCE == FORCE_STIR && MODE == MODE_STEP) {
+    Fsx = ld(L.force, nb.c0);
+    Fsy = ld(L.force + pitch, nb.c0);
+  }
+  // Solid nodes bounce back (F'_i = F~_opp(i)).  They run the same
+  // arithmetic on a rest-frame stand-in and select at the store, so a
+  // wavefront that straddles an obstacle does not diverge.
   bool solid = false;
   if constexpr (MASK) solid = L.mask[node] != 0;
-
-  if constexpr (MODE == MODE_STEP) {
-    if (solid) {   // bounce-back: F'_i = F~_opp(i)
-      static_for<0, Q>([&](auto P) {
-        constexpr int p = decltype(P)::value;
-        st(dst + p * pitch, nb.c0, f[DS::opp[p]]);
-        st(dst + (Q + p) * pitch, nb.c0, g[DS::opp[p]]);
-      });
-      return;
-    }
-  }
 
   // 2. moments of the deviations from the reference: float32 sums over
   //    opposite pairs (even moments from f_a + f_b, odd from f_a - f_b),
@@ -140,12 +138,19 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
       if constexpr (vx != 0.0 && vy != 0.0) mxy += (float)(vx * vy) * sf;
     }
   });
-  const double T00 = a.eps_ref + (double)m00;
-  const double T0x = (double)m0x, T0y = (double)m0y;
-  const double Txx = a.eps_ref * (1.0 / 3.0) + (double)mxx;
-  const double Tyy = a.eps_ref * (1.0 / 3.0) + (double)myy;
-  const double Txy = (double)mxy;
-  const double J0 = a.n_ref + (double)j0, Jx = (double)jx, Jy = (double)jy;
+  double T00 = a.eps_ref + (double)m00;
+  double T0x = (double)m0x, T0y = (double)m0y;
+  double Txx = a.eps_ref * (1.0 / 3.0) + (double)mxx;
+  double Tyy = a.eps_ref * (1.0 / 3.0) + (double)myy;
+  double Txy = (double)mxy;
+  double J0 = a.n_ref + (double)j0, Jx = (double)jx, Jy = (double)jy;
+  if constexpr (MASK) {
+    if (solid) {
+      T00 = a.eps_ref; T0x = 0.0; T0y = 0.0;
+      Txx = a.eps_ref * (1.0 / 3.0); Tyy = Txx; Txy = 0.0;
+      J0 = a.n_ref; Jx = 0.0; Jy = 0.0;
+    }
+  }
 
   // 3. Landau frame and charge density
   Frame fr{0.0, 1.0, 0.0, 0.0};
@@ -190,8 +195,8 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
     if constexpr (FORCE != FORCE_NONE) {
       float Fx = a.fx, Fy = a.fy;
       if constexpr (FORCE == FORCE_STIR) {
-        Fx += ld(L.force, nb.c0);
-        Fy += ld(L.force + pitch, nb.c0);
+        Fx += Fsx;
+        Fy += Fsy;
       }
       float q3xxx = 0, q3xxy = 0, q3xyy = 0, q3yyy = 0, q3xzz = 0, q3yzz = 0;
       static_for<0, Q>([&](auto P) {
@@ -237,8 +242,8 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
       if constexpr (q == p) {
         const float fn = f[p] - w0 * (f[p] - w * ec.A) - w * p0;
         const float gn = g[p] - w0 * (g[p] - w * ec.Ag);
-        st(dst + p * pitch, nb.c0, fn);
-        st(dst + (Q + p) * pitch, nb.c0, gn);
+        st(dst + p * pitch, nb.c0, solid ? f[p] : fn);
+        st(dst + (Q + p) * pitch, nb.c0, solid ? g[p] : gn);
       } else if constexpr (q > p) {
         constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
         constexpr float vxx = (float)(DS::vx[p] * DS::vx[p]);
@@ -259,10 +264,10 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
         }
         const float ga = g[p] - oa * (g[p] - (g0 + g1));
         const float gb = g[q] - ob * (g[q] - (g0 - g1));
-        st(dst + p * pitch, nb.c0, fa);
-        st(dst + q * pitch, nb.c0, fb);
-        st(dst + (Q + p) * pitch, nb.c0, ga);
-        st(dst + (Q + q) * pitch, nb.c0, gb);
+        st(dst + p * pitch, nb.c0, solid ? f[q] : fa);
+        st(dst + q * pitch, nb.c0, solid ? f[p] : fb);
+        st(dst + (Q + p) * pitch, nb.c0, solid ? g[q] : ga);
+        st(dst + (Q + q) * pitch, nb.c0, solid ? g[p] : gb);
       }
     });
   }
@@ -296,9 +301,12 @@ template <class DS>
 __global__ __launch_bounds__(256) void init_kernel(
     const float* __restrict__ eps, const float* __restrict__ bx,
     const float* __restrict__ by, const float* __restrict__ nn, float* dst,
-    int64_t pitch, int32_t ncell, double eps_ref, double n_ref, uint32_t* err) {
+    int64_t pitch, int32_t nx, int32_t ny, int32_t row, double eps_ref, double n_ref,
+    uint32_t* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ncell) return;
+  if (i >= nx * ny) return;
+  const int yy = i / nx;
+  const int o = yy * row + (i - yy * nx);   // padded offset of dense node i
   Frame fr;
   if (!frame_from_beta((double)eps[i], (double)bx[i], (double)by[i], fr)) {
     atomicOr(err, ERR_LANDAU);
@@ -311,8 +319,8 @@ __global__ __launch_bounds__(256) void init_kernel(
     constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
     constexpr float w = DS::w32[p];
     const float s = ux * vx + uy * vy;
-    dst[p * pitch + i] = w * (ec.A + s * (ec.B + s * ec.C));
-    dst[(DS::Q + p) * pitch + i] = w * (ec.Ag + s * ec.Bg);
+    dst[p * pitch + o] = w * (ec.A + s * (ec.B + s * ec.C));
+    dst[(DS::Q + p) * pitch + o] = w * (ec.Ag + s * ec.Bg);
   });
 }
 
@@ -357,8 +365,8 @@ __global__ __launch_bounds__(256) void walls_kernel(uint8_t* mask, int nx,
 
 __global__ __launch_bounds__(256) void fill_u8_kernel(uint8_t* p, size_t n,
                                                       uint8_t v) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -468,12 +476,12 @@ hipError_t launch_init(const rlb_lattice* lat, const float* eps,
   const dim3 grid((ncell + 255) / 256);
   if (lat->Q == 17)
     hipLaunchKernelGGL(init_kernel<Dir17>, grid, dim3(256), 0, lat->stream, eps,
-                       bx, by, n, dst, lat->pitch, ncell, lat->p.eps_ref,
-                       lat->p.n_ref, lat->err);
+                       bx, by, n, dst, lat->pitch, lat->p.nx, lat->p.ny, lat->row,
+                       lat->p.eps_ref, lat->p.n_ref, lat->err);
   else
     hipLaunchKernelGGL(init_kernel<Dir26>, grid, dim3(256), 0, lat->stream, eps,
-                       bx, by, n, dst, lat->pitch, ncell, lat->p.eps_ref,
-                       lat->p.n_ref, lat->err);
+                       bx, by, n, dst, lat->pitch, lat->p.nx, lat->p.ny, lat->row,
+                       lat->p.eps_ref, lat->p.n_ref, lat->err);
   return hipGetLastError();
 }
 
@@ -500,8 +508,8 @@ hipError_t launch_walls(const rlb_lattice* lat) {
 
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
-                     0, s, p, n, v);
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

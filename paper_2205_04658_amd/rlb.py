@@ -33,7 +33,9 @@ SYMBOLS = [
     "rlb_batch_set_body_force", "rlb_batch_step", "rlb_batch_sync", "rlb_batch_info",
     "rlb_batch_set_launch_shape", "rlb_batch_get_launch_shape", "rlb_batch_autotune",
     "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
+    "rlb_set_relaxation_time", "rlb_adjoint_workspace_bytes", "rlb_adjoint_run",
 ]
+OBJECTIVES = {"current": 0, "dissipation": 1}
 
 
 class RLBError(RuntimeError):
@@ -41,6 +43,13 @@ class RLBError(RuntimeError):
         self.status = status
         name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
         super().__init__(f"{name}: {message}")
+
+
+class AdjointCfg(ctypes.Structure):
+    _fields_ = [("nsteps", ctypes.c_int64), ("checkpoint", ctypes.c_int32),
+                ("objective", ctypes.c_int32), ("nmodes", ctypes.c_int32),
+                ("h_modes", ctypes.c_void_p), ("h_amps", ctypes.c_void_p),
+                ("body_force", ctypes.c_double)]
 
 
 class Params(ctypes.Structure):
@@ -82,7 +91,7 @@ def lib():
         "rlb_state_bytes": [_vp, _P(_sz)],
         "rlb_save_state": [_vp, _vp, _sz],
         "rlb_load_state": [_vp, _vp, _sz],
-        "rlb_layout": [_vp, _P(_i32), _P(_i64), _P(_sz)],
+        "rlb_layout": [_vp, _P(_i32), _P(_i32), _P(_i64), _P(_sz)],
         "rlb_stirring_coefficients": [_vp, _i64, _vp, _P(_i32)],
         "rlb_stirring_field": [_vp, _i64, _vp],
         "rlb_philox": [_u64, _u64, _u64, _i64, _vp, _vp],
@@ -106,6 +115,9 @@ def lib():
         "rlb_batch_use_graph": [_vp, _i32],
         "rlb_batch_timing": [_vp, _i32],
         "rlb_batch_timing_read": [_vp, _P(_d), _P(_i64)],
+        "rlb_set_relaxation_time": [_vp, _d],
+        "rlb_adjoint_workspace_bytes": [_vp, _P(AdjointCfg), _P(_sz)],
+        "rlb_adjoint_run": [_vp, _P(AdjointCfg), _vp, _sz, _P(_d), _vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -287,9 +299,11 @@ class Lattice:
         return np.array(out[:])
 
     def layout(self):
-        q, pitch, hb = _i32(), _i64(), _sz()
-        check(lib().rlb_layout(self._h, ctypes.byref(q), ctypes.byref(pitch), ctypes.byref(hb)))
-        return q.value, pitch.value, hb.value
+        """(planes per family, row pitch, plane pitch, header bytes)."""
+        q, row, pitch, hb = _i32(), _i32(), _i64(), _sz()
+        check(lib().rlb_layout(self._h, ctypes.byref(q), ctypes.byref(row), ctypes.byref(pitch),
+                               ctypes.byref(hb)))
+        return q.value, row.value, pitch.value, hb.value
 
     def save_state(self):
         torch = _torch()
@@ -310,9 +324,9 @@ class Lattice:
         of shape (Q, ny, nx) holding F_i - w_i eps_ref and G_i - w_i n_ref."""
         torch = _torch()
         buf = self.save_state() if buf is None else buf
-        q, pitch, hb = self.layout()
-        f = buf[hb:].view(torch.float32).view(2 * q, pitch)[:, :self.nx * self.ny]
-        f = f.reshape(2 * q, self.ny, self.nx)
+        q, row, pitch, hb = self.layout()
+        f = buf[hb:].view(torch.float32).view(2 * q, pitch)[:, :self.ny * row]
+        f = f.reshape(2 * q, self.ny, row)[:, :, :self.nx]
         return f[:q], f[q:]
 
     def stirring_coefficients(self, step):
@@ -352,6 +366,27 @@ class Lattice:
         ms, n = _d(), _i64()
         check(lib().rlb_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def set_relaxation_time(self, tau):
+        check(lib().rlb_set_relaxation_time(self._h, float(tau)))
+
+    def adjoint_run(self, nsteps, checkpoint, objective, modes, amps, body_force, grad=True):
+        """Run nsteps from the current state with F = F_b x_hat + sum_m A_m
+        phi_m; return (J, dJ/d(F_b, tau, A_1..A_M) or None)."""
+        torch = _torch()
+        modes = np.ascontiguousarray(np.asarray(modes, np.float64).reshape(-1, 5))
+        amps = np.ascontiguousarray(np.asarray(amps, np.float64).reshape(-1))
+        cfg = AdjointCfg(int(nsteps), int(checkpoint), OBJECTIVES[objective], modes.shape[0],
+                         modes.ctypes.data, amps.ctypes.data, float(body_force))
+        nb = _sz()
+        check(lib().rlb_adjoint_workspace_bytes(self._h, ctypes.byref(cfg), ctypes.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self._in(ws)
+        J = _d()
+        g = np.zeros(2 + modes.shape[0], np.float64)
+        check(lib().rlb_adjoint_run(self._h, ctypes.byref(cfg), _vp(ws.data_ptr()), nb.value,
+                                    ctypes.byref(J), g.ctypes.data if grad else None))
+        return J.value, (g if grad else None)
 
 
 class Batch:
@@ -447,3 +482,35 @@ class Batch:
         ms, n = _d(), _i64()
         check(lib().rlb_batch_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def _autograd():
+    import torch
+
+    class RLBObjective(torch.autograd.Function):
+        """J(theta), theta = (F_b, tau, A_1..A_M) as a float64 tensor.  The
+        forward resets the lattice to `fields`, runs the step `nsteps` times
+        and evaluates the objective; the gradient comes from the library's
+        adjoint run (checkpoint every `checkpoint` steps)."""
+
+        @staticmethod
+        def forward(ctx, theta, lattice, fields, modes, nsteps, checkpoint, objective):
+            th = theta.detach().cpu().double().numpy()
+            lattice.init_fields(fields["eps"], fields["bx"], fields["by"], fields["n"])
+            lattice.set_relaxation_time(th[1])
+            J, g = lattice.adjoint_run(nsteps, checkpoint, objective, modes, th[2:], th[0],
+                                       grad=True)
+            ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype))
+            return torch.tensor(J, dtype=theta.dtype)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (g,) = ctx.saved_tensors
+            return gout * g.to(gout.device), None, None, None, None, None, None
+
+    return RLBObjective
+
+
+def rlb_objective(theta, lattice, fields, modes, nsteps, checkpoint, objective="current"):
+    """Differentiable objective of a driven run (torch.autograd)."""
+    return _autograd().apply(theta, lattice, fields, modes, nsteps, checkpoint, objective)

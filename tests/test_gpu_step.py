@@ -138,11 +138,14 @@ def test_conservation_drift():
     t0 = lat.conserved()
     lat.step(1000)
     t1 = lat.conserved()
-    # float32 populations: the drift is rounding only (no systematic bias)
+    # float32 populations: the drift is rounding only.  Rounding of nearly
+    # equal values at neighbouring nodes is coherent, so it does not average
+    # out like a random walk; measured 1e-9 .. 2e-9 relative per 1000 steps
+    # (a systematic bias from float32 weights was 3e-8 and is removed)
     E = t0[0]
-    assert abs(t1[0] - t0[0]) < 2e-9 * E, (t1 - t0) / E
-    assert np.abs(t1[1:3] - t0[1:3]).max() < 2e-9 * E, (t1 - t0) / E
-    assert abs(t1[3] - t0[3]) < 2e-9 * t0[3], (t1 - t0) / t0[3]
+    assert abs(t1[0] - t0[0]) < 5e-9 * E, (t1 - t0) / E
+    assert np.abs(t1[1:3] - t0[1:3]).max() < 5e-9 * E, (t1 - t0) / E
+    assert abs(t1[3] - t0[3]) < 5e-9 * t0[3], (t1 - t0) / t0[3]
 
 
 def test_determinism_and_resume():
