@@ -27,7 +27,8 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % HBM peak, 4096² forced RLB; batched/adjoint vs plain, same GPU"
 KERNEL_SOURCES = ["paper_2205_04658_amd/csrc/step.hip", "paper_2205_04658_amd/csrc/device_common.hpp",
                   "paper_2205_04658_amd/csrc/forcing.hip",
-                  "paper_2205_04658_amd/csrc/dirset.hpp", "paper_2205_04658_amd/csrc/internal.hpp"]
+                  "paper_2205_04658_amd/csrc/dirset.hpp", "paper_2205_04658_amd/csrc/internal.hpp",
+                  "paper_2205_04658_amd/csrc/brick.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_forced4096_traffic.json")
 
 
@@ -109,7 +110,7 @@ print(json.dumps(dict(steps=steps, seconds=el, cells=n * n)))
                       f"{d['steps']} steps in {d['seconds']:.1f} s, float64 NumPy, 1 thread"}
 
 
-def run_plain(torch, rlb, workloads, layout, steps, warmup):
+def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None):
     c = workloads.FORCED_4096
     nx, ny = c["nx"], c["ny"]
     lat = rlb.Lattice(nx, ny, c["tau"], full26=(layout == "full26"), eps_ref=c["eps"], n_ref=c["n"])
@@ -117,7 +118,11 @@ def run_plain(torch, rlb, workloads, layout, steps, warmup):
     lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
     lat.set_stirring(c["kmin"], c["kmax"], c["amplitude"], c["seed"])
     lat.step(2)
-    tune = lat.autotune(trials=5)          # keeps the fastest launch shape
+    if shape is None:
+        tune = lat.autotune(trials=5)      # keeps the fastest launch shape
+    else:                                  # a fixed shape (profiling runs)
+        lat.set_launch_shape(*shape)
+        tune = []
     lat.step(warmup)
     lat.sync()
     lat.timing(True)
@@ -240,6 +245,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--shape", default=None,
+                    help="tile_rows,grid_per_cu,strip: fixed launch shape instead of the autotuner")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -248,7 +255,8 @@ def main():
     from paper_2205_04658_amd import rlb, workloads
     rlb.lib()
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
-    main_run = run_plain(torch, rlb, workloads, a.layout, a.steps, a.warmup)
+    shape = tuple(int(v) for v in a.shape.split(",")) if a.shape else None
+    main_run = run_plain(torch, rlb, workloads, a.layout, a.steps, a.warmup, shape)
     variants = {}
     if not a.no_variants:
         other = "full26" if a.layout == "folded17" else "folded17"
@@ -275,7 +283,8 @@ def main():
         "config": {"workload": "forced turbulence 4096x4096 periodic, tau 0.52, stirring "
                                "31<=|k|<=33 (412 modes), amplitude 5e-6, seed 4658",
                    "layout": r["layout"], "planes_per_family": r["planes"],
-                   "launch_shape": {"tile_rows": r["shape"][0], "grid_per_cu": r["shape"][1]},
+                   "launch_shape": {"tile_rows": r["shape"][0], "grid_per_cu": r["shape"][1],
+                                    "strip": r["shape"][2]},
                    "precision": "f32 populations (shifted), f64 Landau solve and reductions",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS,

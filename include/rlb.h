@@ -177,12 +177,16 @@ rlb_status rlb_state_bytes(const rlb_lattice* lat, size_t* bytes);
 rlb_status rlb_save_state(rlb_lattice* lat, void* d_buf, size_t bytes);
 rlb_status rlb_load_state(rlb_lattice* lat, const void* d_buf, size_t bytes);
 
-/* Layout of the population planes in saved states: `planes` per family (17
- * or 26), each plane [ny][row_pitch] float32 (row_pitch = nx rounded up to
- * 64, so every row starts on a 256-byte boundary; columns nx.. are unused),
- * plane k at byte header_bytes + 4 * k * pitch.  F planes come first. */
+/* Layout of the populations in saved states (and on the device): `planes`
+ * per family (17 or 26; F planes 0..planes-1 first, then G), stored as node
+ * bricks.  row_pitch = nx rounded up to 64 (columns nx.. are unused);
+ * row_stride = 2 * planes * row_pitch.  Plane k of node (x, y) is the
+ * float32 at element
+ *   y * row_stride + (x / 64) * (2 * planes * 64) + k * 64 + x % 64
+ * after header_bytes: each run of 64 columns of a row keeps its 2 * planes
+ * planes together, 256 bytes per plane. */
 rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitch,
-                      int64_t* pitch, size_t* header_bytes);
+                      int64_t* row_stride, size_t* header_bytes);
 
 /* Stirring coefficients of a given step without advancing anything:
  * d_out[4m .. 4m+3] = (Re Fx_hat, Im Fx_hat, Re Fy_hat, Im Fy_hat) of mode
@@ -209,18 +213,24 @@ rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches
 
 /* Launch shape of the step kernel: tiles of 64 x tile_rows nodes (one
  * wavefront per row; tile_rows in {1, 2, 4, 8}, other than 4 only for the
- * folded layout) and the grid: grid_per_cu = 0 launches one workgroup per
+ * folded layout); the grid: grid_per_cu = 0 launches one workgroup per
  * tile, k > 0 launches about k resident workgroups of 4 wavefronts per CU
- * that walk the tile list.  Results do not depend on the shape (bitwise). */
-rlb_status rlb_set_launch_shape(rlb_lattice* lat, int32_t tile_rows, int32_t grid_per_cu);
-rlb_status rlb_get_launch_shape(const rlb_lattice* lat, int32_t* tile_rows, int32_t* grid_per_cu);
+ * that walk the tile list; and the tile order: a lattice's tiles are
+ * visited in vertical strips `strip` tiles wide (1..65536; the last strip
+ * may be narrower), row by row inside a strip, the eight XCDs each taking
+ * a contiguous share of that order.  Results do not depend on the shape
+ * (bitwise). */
+rlb_status rlb_set_launch_shape(rlb_lattice* lat, int32_t tile_rows, int32_t grid_per_cu,
+                                int32_t strip);
+rlb_status rlb_get_launch_shape(const rlb_lattice* lat, int32_t* tile_rows, int32_t* grid_per_cu,
+                                int32_t* strip);
 
 /* Autotuner: time `trials` step-kernel launches for every candidate shape
- * (tile_rows x grid_per_cu in {0, 2, 4, 8}) on the current state -- each
- * launch reads the current copy and overwrites the other, so the state does
- * not advance -- and keep the fastest.  If h_ms is not null, up to
- * max_results rows (tile_rows, grid_per_cu, ms per launch) are written.
- * Synchronises. */
+ * (tile_rows x grid_per_cu in {0, 4} x strip in {4, 8, 16, 32}) on the
+ * current state -- each launch reads the current copy and overwrites the
+ * other, so the state does not advance -- and keep the fastest.  If h_ms
+ * is not null, up to max_results rows (tile_rows, grid_per_cu, strip, ms
+ * per launch) of 4 doubles are written.  Synchronises. */
 rlb_status rlb_autotune(rlb_lattice* lat, int32_t trials, double* h_ms, int32_t max_results);
 
 /* ------------------------------------------------------------------------
@@ -271,9 +281,10 @@ rlb_status rlb_batch_info(const rlb_batch* batch, int32_t* count, int64_t* cells
 /* Launch shape (as rlb_set_launch_shape) and autotuner (as rlb_autotune)
  * of the batched step; graph replay of steps_per_graph (even, 0 = off,
  * default 16) steps per launch. */
-rlb_status rlb_batch_set_launch_shape(rlb_batch* batch, int32_t tile_rows, int32_t grid_per_cu);
+rlb_status rlb_batch_set_launch_shape(rlb_batch* batch, int32_t tile_rows, int32_t grid_per_cu,
+                                      int32_t strip);
 rlb_status rlb_batch_get_launch_shape(const rlb_batch* batch, int32_t* tile_rows,
-                                      int32_t* grid_per_cu);
+                                      int32_t* grid_per_cu, int32_t* strip);
 rlb_status rlb_batch_autotune(rlb_batch* batch, int32_t trials, double* h_ms, int32_t max_results);
 rlb_status rlb_batch_use_graph(rlb_batch* batch, int32_t steps_per_graph);
 

@@ -23,68 +23,9 @@
 #include "internal.hpp"
 #include "device_common.hpp"
 #include "dirset.hpp"
+#include "brick.hpp"
 
 namespace rlb {
-
-template <class DS, int P>
-struct TapsA {
-  static constexpr double vx = DS::vx[P], vy = DS::vy[P];
-  static constexpr int sx = vx > 0 ? 1 : (vx < 0 ? -1 : 0);
-  static constexpr int sy = vy > 0 ? 1 : (vy < 0 ? -1 : 0);
-  static constexpr bool unit_x = vx == 1.0 || vx == -1.0;
-  static constexpr bool unit_y = vy == 1.0 || vy == -1.0;
-};
-
-struct NbrA {
-  uint32_t c0, cxm, cxp, ym0, ymxm, ymxp, yp0, ypxm, ypxp;
-};
-
-__device__ __forceinline__ float lda(const float* plane, uint32_t off) {
-  return *(const float*)((const char*)plane + off);
-}
-
-// Pull (REV = false): value at x of the field taken at x - delta.  The
-// transposed pull (REV = true) takes the same weights at x + delta.
-template <class DS, bool UNIT, int P, bool REV>
-__device__ __forceinline__ float pull_a(const float* __restrict__ pl, const StepShared& a,
-                                        const NbrA& n) {
-  using T = TapsA<DS, P>;
-  constexpr int sx = REV ? -T::sx : T::sx;
-  constexpr int sy = REV ? -T::sy : T::sy;
-  const uint32_t c_x = sx > 0 ? n.cxm : n.cxp;
-  const uint32_t c_y = sy > 0 ? n.ym0 : n.yp0;
-  const uint32_t c_xy = sy > 0 ? (sx > 0 ? n.ymxm : n.ymxp) : (sx > 0 ? n.ypxm : n.ypxp);
-  if constexpr (T::sx == 0 && T::sy == 0) {
-    return lda(pl, n.c0);
-  } else if constexpr (UNIT && T::unit_x) {
-    return lda(pl, c_x);
-  } else if constexpr (UNIT && T::unit_y) {
-    return lda(pl, c_y);
-  } else if constexpr (T::sy == 0) {
-    return a.tap[P][0] * lda(pl, n.c0) + a.tap[P][1] * lda(pl, c_x);
-  } else if constexpr (T::sx == 0) {
-    return a.tap[P][0] * lda(pl, n.c0) + a.tap[P][2] * lda(pl, c_y);
-  } else {
-    return a.tap[P][0] * lda(pl, n.c0) + a.tap[P][1] * lda(pl, c_x) +
-           a.tap[P][2] * lda(pl, c_y) + a.tap[P][3] * lda(pl, c_xy);
-  }
-}
-
-// Padded byte offsets of the 3x3 neighbourhood (rows of `row` elements) and
-// the dense node index y * nx + x.
-__device__ __forceinline__ NbrA neighbours(int x, int y, int nx, int ny, int row, uint32_t& node) {
-  const int xm = x == 0 ? nx - 1 : x - 1;
-  const int xp = x == nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1;
-  const int yp = y == ny - 1 ? 0 : y + 1;
-  const uint32_t r0 = (uint32_t)(y * row), rm = (uint32_t)(ym * row), rp = (uint32_t)(yp * row);
-  NbrA nb;
-  nb.c0 = 4u * (r0 + x);  nb.cxm = 4u * (r0 + xm); nb.cxp = 4u * (r0 + xp);
-  nb.ym0 = 4u * (rm + x); nb.ymxm = 4u * (rm + xm); nb.ymxp = 4u * (rm + xp);
-  nb.yp0 = 4u * (rp + x); nb.ypxm = 4u * (rp + xm); nb.ypxp = 4u * (rp + xp);
-  node = (uint32_t)(y * nx + x);
-  return nb;
-}
 
 // Solve M z = b (4x4, partial pivoting), float64.
 __device__ __forceinline__ void solve4(double M[4][4], double b[4]) {
@@ -173,27 +114,25 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   const int x = (tile - ty * a.tiles_x) * 64 + (threadIdx.x & 63);
   const int y = __builtin_amdgcn_readfirstlane(ty * 4 + (threadIdx.x >> 6));
   if (x >= a.nx || y >= a.ny) return;
-  uint32_t node;
-  const NbrA nb = neighbours(x, y, a.nx, a.ny, a.row, node);
-  const int64_t pitch = a.pitch;
+  const uint32_t node = (uint32_t)(y * a.nx + x);
+  const Nbr nb = neighbourhood<Q>(x, y, a.nx, a.ny, a.row);
   const StepShared& sh = a.sh;
 
   float f[Q], g[Q], lf[Q], lg[Q];
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
-    f[p] = pull_a<DS, UNIT, p, false>(a.state + p * pitch, sh, nb);
-    g[p] = pull_a<DS, UNIT, p, false>(a.state + (Q + p) * pitch, sh, nb);
+    f[p] = pull<DS, UNIT, p, p, false>(a.state, nb, sh.tap[p]);
+    g[p] = pull<DS, UNIT, p, Q + p, false>(a.state, nb, sh.tap[p]);
     if (a.mu_in) {
-      lf[p] = pull_a<DS, UNIT, p, true>(a.mu_in + p * pitch, sh, nb);
-      lg[p] = pull_a<DS, UNIT, p, true>(a.mu_in + (Q + p) * pitch, sh, nb);
+      lf[p] = pull<DS, UNIT, p, p, true>(a.mu_in, nb, sh.tap[p]);
+      lg[p] = pull<DS, UNIT, p, Q + p, true>(a.mu_in, nb, sh.tap[p]);
     } else {
       lf[p] = 0.0f;
       lg[p] = 0.0f;
     }
   });
-  float* out = a.mu_out;
-  const uint32_t o4 = nb.c0;
-  auto put = [&](int plane, float v) { *(float*)((char*)(out + plane * pitch) + o4) = v; };
+  char* out = (char*)a.mu_out + nb.r[1] + nb.c[1];
+  auto put = [&](int plane, float v) { *(float*)(out + plane * 256) = v; };
 
   if constexpr (MASK) {
     if (a.mask[node]) {   // f'_p = f~_opp(p): mu_q = lambda'_opp(q)
@@ -223,8 +162,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   const EqCoef ec = eq_coef(fr, n, sh.eps_ref, sh.n_ref, DS::kappa);
   const float ux = (float)fr.ux, uy = (float)fr.uy, u0 = (float)fr.u0;
   const float itau = sh.inv_tau;
-  const float Fx = sh.fx + lda(a.force, nb.c0);
-  const float Fy = sh.fy + lda(a.force + pitch, nb.c0);
+  const gfloat* frc = (const gfloat*)a.force + (int64_t)y * a.row + x;
+  const float Fx = sh.fx + frc[0];
+  const float Fy = sh.fy + frc[a.pitch];
   float q3xxx = 0, q3xxy = 0, q3xyy = 0, q3yyy = 0, q3xzz = 0, q3yzz = 0;
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
@@ -391,13 +331,12 @@ __global__ __launch_bounds__(256) void objective_kernel(const ObjArgs a) {
     if constexpr (MASK) {
       if (a.mask[i]) continue;
     }
-    uint32_t node;
-    const NbrA nb = neighbours(x, y, a.nx, a.ny, a.row, node);
+    const Nbr nb = neighbourhood<Q>(x, y, a.nx, a.ny, a.row);
     float f[Q], g[Q];
     static_for<0, Q>([&](auto P) {
       constexpr int p = decltype(P)::value;
-      f[p] = pull_a<DS, UNIT, p, false>(a.state + p * a.pitch, a.sh, nb);
-      g[p] = pull_a<DS, UNIT, p, false>(a.state + (Q + p) * a.pitch, a.sh, nb);
+      f[p] = pull<DS, UNIT, p, p, false>(a.state, nb, a.sh.tap[p]);
+      g[p] = pull<DS, UNIT, p, Q + p, false>(a.state, nb, a.sh.tap[p]);
     });
     const Moments m = moments_of<DS>(f, g, a.sh.eps_ref, a.sh.n_ref);
     if (a.kind == 2) {

@@ -240,8 +240,7 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   lat->dstep = (int64_t*)(lat->ws + w.misc_off + 64);
   lat->d_desc = (LatDesc*)(lat->ws + w.desc_off);
   lat->num_cu = prop.multiProcessorCount;
-  lat->shape.tile_rows = 4;
-  lat->shape.grid_per_cu = 0;
+  lat->shape = LaunchShape{4, 0, 16};
   lat->desc.state[0] = lat->state[0];
   lat->desc.state[1] = lat->state[1];
   lat->desc.mask = lat->mask;
@@ -477,12 +476,12 @@ rlb_status rlb_state_bytes(const rlb_lattice* lat, size_t* bytes) {
   return RLB_OK;
 }
 
-rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitch, int64_t* pitch,
-                      size_t* header_bytes) {
+rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitch,
+                      int64_t* row_stride, size_t* header_bytes) {
   if (rlb_status s = check_lat(lat)) return s;
   if (planes) *planes = lat->Q;
   if (row_pitch) *row_pitch = lat->row;
-  if (pitch) *pitch = lat->pitch;
+  if (row_stride) *row_stride = (int64_t)2 * lat->Q * lat->row;
   if (header_bytes) *header_bytes = kHeaderBytes;
   return RLB_OK;
 }
@@ -603,20 +602,23 @@ rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches
   return RLB_OK;
 }
 
-rlb_status rlb_set_launch_shape(rlb_lattice* lat, int32_t tile_rows, int32_t grid_per_cu) {
+rlb_status rlb_set_launch_shape(rlb_lattice* lat, int32_t tile_rows, int32_t grid_per_cu,
+                                int32_t strip) {
   if (rlb_status s = check_lat(lat)) return s;
   if (!(tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8))
     return fail(RLB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
   if (grid_per_cu < 0 || grid_per_cu > 64) return fail(RLB_EINVAL, "grid_per_cu must be in [0, 64]");
-  lat->shape.tile_rows = tile_rows;
-  lat->shape.grid_per_cu = grid_per_cu;
+  if (strip < 1 || strip > 65536) return fail(RLB_EINVAL, "strip must be in [1, 65536]");
+  lat->shape = LaunchShape{tile_rows, grid_per_cu, strip};
   return RLB_OK;
 }
 
-rlb_status rlb_get_launch_shape(const rlb_lattice* lat, int32_t* tile_rows, int32_t* grid_per_cu) {
+rlb_status rlb_get_launch_shape(const rlb_lattice* lat, int32_t* tile_rows, int32_t* grid_per_cu,
+                                int32_t* strip) {
   if (rlb_status s = check_lat(lat)) return s;
   if (tile_rows) *tile_rows = lat->shape.tile_rows;
   if (grid_per_cu) *grid_per_cu = lat->shape.grid_per_cu;
+  if (strip) *strip = lat->shape.strip;
   return RLB_OK;
 }
 
@@ -632,10 +634,7 @@ rlb_status rlb_autotune(rlb_lattice* lat, int32_t trials, double* h_ms, int32_t 
     }
     return hipSuccess;
   };
-  std::vector<LaunchShape> cand;
-  for (int ty : {1, 2, 4, 8})
-    for (int g : {0, 2, 4, 8})
-      if (lat->Q == 17 || ty == 4) cand.push_back(LaunchShape{ty, g});
+  const std::vector<LaunchShape> cand = launch_candidates(lat->Q);
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "event");
   HIP_TRY(hipEventCreate(&e1), "event");
@@ -659,9 +658,10 @@ rlb_status rlb_autotune(rlb_lattice* lat, int32_t trials, double* h_ms, int32_t 
     }
     const double per = ms / trials;
     if (h_ms && k < max_results) {
-      h_ms[3 * k] = c.tile_rows;
-      h_ms[3 * k + 1] = c.grid_per_cu;
-      h_ms[3 * k + 2] = per;
+      h_ms[4 * k] = c.tile_rows;
+      h_ms[4 * k + 1] = c.grid_per_cu;
+      h_ms[4 * k + 2] = c.strip;
+      h_ms[4 * k + 3] = per;
     }
     ++k;
     if (per < best_ms) { best_ms = per; win = c; }

@@ -225,7 +225,7 @@ rlb_status rlb_batch_create(const rlb_params* p, int32_t count, const int32_t* h
   B->ws = (char*)d_workspace;
   B->ws_bytes = bytes;
   B->stream = (hipStream_t)hip_stream;
-  B->shape = LaunchShape{4, 0};
+  B->shape = LaunchShape{4, 0, 16};
   B->graph_steps = 16;
   for (int b = 0; b < count; ++b) {
     rlb_params q = *p;
@@ -294,21 +294,25 @@ rlb_status rlb_batch_set_body_force(rlb_batch* B, double fx, double fy) {
   return RLB_OK;
 }
 
-rlb_status rlb_batch_set_launch_shape(rlb_batch* B, int32_t tile_rows, int32_t grid_per_cu) {
+rlb_status rlb_batch_set_launch_shape(rlb_batch* B, int32_t tile_rows, int32_t grid_per_cu,
+                                      int32_t strip) {
   if (rlb_status s = check_batch(B)) return s;
   if (!(tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8))
     return bfail(RLB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
   if (B->Q != 17 && tile_rows != 4) return bfail(RLB_EUNSUPPORTED, "tile_rows != 4 needs the folded layout");
   if (grid_per_cu < 0 || grid_per_cu > 64) return bfail(RLB_EINVAL, "grid_per_cu must be in [0, 64]");
+  if (strip < 1 || strip > 65536) return bfail(RLB_EINVAL, "strip must be in [1, 65536]");
   drop_graph(B);
-  B->shape = LaunchShape{tile_rows, grid_per_cu};
+  B->shape = LaunchShape{tile_rows, grid_per_cu, strip};
   return build_tables(B, tile_rows);
 }
 
-rlb_status rlb_batch_get_launch_shape(const rlb_batch* B, int32_t* tile_rows, int32_t* grid_per_cu) {
+rlb_status rlb_batch_get_launch_shape(const rlb_batch* B, int32_t* tile_rows, int32_t* grid_per_cu,
+                                      int32_t* strip) {
   if (rlb_status s = check_batch(B)) return s;
   if (tile_rows) *tile_rows = B->shape.tile_rows;
   if (grid_per_cu) *grid_per_cu = B->shape.grid_per_cu;
+  if (strip) *strip = B->shape.strip;
   return RLB_OK;
 }
 
@@ -408,10 +412,7 @@ rlb_status rlb_batch_autotune(rlb_batch* B, int32_t trials, double* h_ms, int32_
   const bool mask = any_solid(B);
   const int force = force_mode(B);
   drop_graph(B);
-  std::vector<LaunchShape> cand;
-  for (int ty : {1, 2, 4, 8})
-    for (int g : {0, 2, 4, 8})
-      if (B->Q == 17 || ty == 4) cand.push_back(LaunchShape{ty, g});
+  const std::vector<LaunchShape> cand = launch_candidates(B->Q);
   hipEvent_t e0, e1;
   BHIP(hipEventCreate(&e0), "event");
   BHIP(hipEventCreate(&e1), "event");
@@ -437,9 +438,10 @@ rlb_status rlb_batch_autotune(rlb_batch* B, int32_t trials, double* h_ms, int32_
     }
     const double per = ms / trials;
     if (h_ms && k < max_results) {
-      h_ms[3 * k] = c.tile_rows;
-      h_ms[3 * k + 1] = c.grid_per_cu;
-      h_ms[3 * k + 2] = per;
+      h_ms[4 * k] = c.tile_rows;
+      h_ms[4 * k + 1] = c.grid_per_cu;
+      h_ms[4 * k + 2] = c.strip;
+      h_ms[4 * k + 3] = per;
     }
     ++k;
     if (per < best) {

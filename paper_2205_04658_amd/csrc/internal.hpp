@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/rlb.h"
 
@@ -41,12 +42,14 @@ struct StepShared {
 };
 
 // One lattice as the tile kernel sees it (device memory, read with scalar
-// loads).  state[c] are the two ping-pong copies of the 2Q planes.
+// loads).  state[c] are the two ping-pong state copies (node bricks, see
+// brick.hpp); the two stirring-force planes are plain [ny][row] arrays
+// `pitch` elements apart.
 struct LatDesc {
   const float* state[2];
   const uint8_t* mask;    // [ny][nx] solid flags (used when MASK)
   const float* force;     // two stirring-force planes (FORCE_STIR)
-  int64_t pitch;          // plane pitch in elements
+  int64_t pitch;          // force-plane pitch in elements
   int32_t nx, ny;
   int32_t tiles_x;        // tiles per row of tiles
   int32_t tile_begin;     // first global tile index of this lattice
@@ -62,6 +65,7 @@ struct TileArgs {
   int32_t tile_first;       // tile range of this launch
   int32_t ntiles;
   int32_t tiles_per_xcd;    // ceil(ntiles / 8)
+  int32_t strip;            // tile-order strip width in tiles (>= 1)
   float* fields;            // MODE_FIELDS output [k][ny][nx]
 };
 
@@ -71,6 +75,7 @@ struct TileArgs {
 struct LaunchShape {
   int32_t tile_rows;
   int32_t grid_per_cu;
+  int32_t strip;          // tiles are ordered in vertical strips this many tiles wide
 };
 
 struct StirArgs {
@@ -92,11 +97,11 @@ struct StirArgs {
 // Adjoint kernels (adjoint.hip).
 struct AdjArgs {
   StepShared sh;
-  const float* state;     // s_t planes [2Q][pitch]
+  const float* state;     // s_t (node bricks)
   const float* mu_in;     // mu_{t+1} (null: zero)
   float* mu_out;          // mu_t
   const uint8_t* mask;    // solid flags [ny][nx] or null
-  const float* force;     // static stirring-basis planes [2][pitch]
+  const float* force;     // static stirring-basis planes [2][pitch], rows of `row`
   double2* acc_f;         // per-node sum of dJ/dF(x), dense [ny][nx]
   double* acc_itau;       // per-node sum of dJ/d(1/tau)
   int64_t pitch;
@@ -181,6 +186,9 @@ hipError_t launch_tiles(int Q, bool unit, bool mask, int mode, int force_mode,
                         const TileArgs& a, LaunchShape shape, int num_cu,
                         hipStream_t s);
 int tiles_of(int nx, int ny, int tile_rows);
+// Launch shapes the autotuners time (tile heights other than 4 only for the
+// folded set).
+std::vector<LaunchShape> launch_candidates(int Q);
 hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode,
                        int parity, float* fields, uint32_t field_mask);
 hipError_t launch_init(const rlb_lattice* lat, const float* eps,

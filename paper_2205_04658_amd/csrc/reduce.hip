@@ -7,6 +7,7 @@
 #include "dirset.hpp"
 #include "internal.hpp"
 #include "device_common.hpp"
+#include "brick.hpp"
 
 namespace rlb {
 
@@ -18,7 +19,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 template <class DS>
 __global__ __launch_bounds__(256) void totals_kernel(const float* __restrict__ st,
-                                                     int64_t pitch, int nx, int ny, int row,
+                                                     int nx, int ny, int row,
                                                      double* partial) {
   constexpr int Q = DS::Q;
   double e = 0.0, px = 0.0, py = 0.0, q = 0.0;
@@ -26,14 +27,14 @@ __global__ __launch_bounds__(256) void totals_kernel(const float* __restrict__ s
   const int ncell = nx * ny;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ncell; j += stride) {
     const int yy = j / nx;
-    const int i = yy * row + (j - yy * nx);   // padded offset
+    const float* b = st + state_elem<Q>(0, j - yy * nx, yy, row);   // plane 0 of node j
     static_for<0, Q>([&](auto P) {
       constexpr int p = decltype(P)::value;
-      const double f = (double)st[p * pitch + i];
+      const double f = (double)b[p * 64];
       e += f;
       if constexpr (DS::vx[p] != 0.0) px += DS::vx[p] * f;
       if constexpr (DS::vy[p] != 0.0) py += DS::vy[p] * f;
-      q += (double)st[(Q + p) * pitch + i];
+      q += (double)b[(Q + p) * 64];
     });
   }
   __shared__ double red[4][4];
@@ -89,11 +90,11 @@ hipError_t launch_totals(const rlb_lattice* lat, const float* state,
   const int ncell = lat->p.nx * lat->p.ny;
   if (lat->Q == 17)
     hipLaunchKernelGGL(totals_kernel<Dir17>, dim3(kRedBlocks), dim3(256), 0,
-                       lat->stream, state, lat->pitch, lat->p.nx, lat->p.ny, lat->row,
+                       lat->stream, state, lat->p.nx, lat->p.ny, lat->row,
                        lat->partials);
   else
     hipLaunchKernelGGL(totals_kernel<Dir26>, dim3(kRedBlocks), dim3(256), 0,
-                       lat->stream, state, lat->pitch, lat->p.nx, lat->p.ny, lat->row,
+                       lat->stream, state, lat->p.nx, lat->p.ny, lat->row,
                        lat->partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -3,8 +3,10 @@
 // bounce-back at solid nodes; plus the field read-out and initialisation
 // kernels that reuse its pieces.
 //
-// Layout: 2Q float32 planes [plane][ny][nx] (F planes 0..Q-1, G planes
-// Q..2Q-1), x fastest, plane pitch a multiple of 64 elements.  One thread
+// Layout: node bricks (brick.hpp): each lattice row is a run of 64-node
+// bricks holding the 2Q planes of their nodes (F planes 0..Q-1, then G
+// planes Q..2Q-1).  The stirring force keeps two plain [ny][row] planes.
+// One thread
 // per node; a tile is 64 x TY nodes, one wavefront per row, so row-uniform
 // quantities are scalar.  A launch walks a list of tiles that may span many
 // lattices (the batched path): each tile names its lattice, whose
@@ -17,58 +19,9 @@
 #include "internal.hpp"
 #include "device_common.hpp"
 #include "dirset.hpp"
+#include "brick.hpp"
 
 namespace rlb {
-
-template <class DS, int P>
-struct Taps {
-  static constexpr double vx = DS::vx[P], vy = DS::vy[P];
-  static constexpr int sx = vx > 0 ? 1 : (vx < 0 ? -1 : 0);
-  static constexpr int sy = vy > 0 ? 1 : (vy < 0 ? -1 : 0);
-  static constexpr bool unit_x = vx == 1.0 || vx == -1.0;
-  static constexpr bool unit_y = vy == 1.0 || vy == -1.0;
-};
-
-// Per-lane byte offsets of the 3x3 neighbourhood inside one plane.  Offsets
-// are 32-bit and the plane base is wave-uniform, so every load and store is
-// a scalar-base + vector-offset access with no per-lane 64-bit arithmetic.
-struct Nbr {
-  uint32_t c0, cxm, cxp, ym0, ymxm, ymxp, yp0, ypxm, ypxp;
-};
-
-__device__ __forceinline__ float ld(const float* plane, uint32_t off) {
-  return *(const float*)((const char*)plane + off);
-}
-
-// Pull value of plane P at the node: bilinear interpolation of the
-// pre-stream plane at the departure point (x, y) - cfl (vx, vy).
-template <class DS, bool UNIT, int P>
-__device__ __forceinline__ float pull(const float* __restrict__ pl,
-                                      const StepShared& a, const Nbr& n) {
-  using T = Taps<DS, P>;
-  const uint32_t c_x = T::sx > 0 ? n.cxm : n.cxp;              // (x - sx, y)
-  const uint32_t c_y = T::sy > 0 ? n.ym0 : n.yp0;              // (x, y - sy)
-  const uint32_t c_xy = T::sy > 0 ? (T::sx > 0 ? n.ymxm : n.ymxp)
-                                  : (T::sx > 0 ? n.ypxm : n.ypxp);
-  if constexpr (T::sx == 0 && T::sy == 0) {
-    return ld(pl, n.c0);
-  } else if constexpr (UNIT && T::unit_x) {
-    return ld(pl, c_x);                    // full step along x
-  } else if constexpr (UNIT && T::unit_y) {
-    return ld(pl, c_y);                    // full step along y
-  } else if constexpr (T::sy == 0) {
-    return a.tap[P][0] * ld(pl, n.c0) + a.tap[P][1] * ld(pl, c_x);
-  } else if constexpr (T::sx == 0) {
-    return a.tap[P][0] * ld(pl, n.c0) + a.tap[P][2] * ld(pl, c_y);
-  } else {
-    return a.tap[P][0] * ld(pl, n.c0) + a.tap[P][1] * ld(pl, c_x) +
-           a.tap[P][2] * ld(pl, c_y) + a.tap[P][3] * ld(pl, c_xy);
-  }
-}
-
-__device__ __forceinline__ void st(float* plane, uint32_t off, float v) {
-  __builtin_nontemporal_store(v, (float*)((char*)plane + off));
-}
 
 template <class DS, bool UNIT, bool MASK, int FORCE, int MODE>
 __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc& L,
@@ -77,17 +30,8 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
                                             float* __restrict__ fields, int x, int y) {
   constexpr int Q = DS::Q;
   const int nx = L.nx, ny = L.ny;
-  const int64_t pitch = L.pitch;
-  const int xm = x == 0 ? nx - 1 : x - 1;
-  const int xp = x == nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1;
-  const int yp = y == ny - 1 ? 0 : y + 1;
-  const int row = L.row;   // row pitch: rows start on 256-byte boundaries
-  const uint32_t r0 = (uint32_t)(y * row), rm = (uint32_t)(ym * row), rp = (uint32_t)(yp * row);
-  Nbr nb;
-  nb.c0 = 4u * (r0 + x);   nb.cxm = 4u * (r0 + xm); nb.cxp = 4u * (r0 + xp);
-  nb.ym0 = 4u * (rm + x);  nb.ymxm = 4u * (rm + xm); nb.ymxp = 4u * (rm + xp);
-  nb.yp0 = 4u * (rp + x);  nb.ypxm = 4u * (rp + xm); nb.ypxp = 4u * (rp + xp);
+  const int row = L.row;   // nx rounded up to 64
+  const Nbr nb = neighbourhood<Q>(x, y, nx, ny, row);
   const uint32_t node = (uint32_t)(y * nx + x);   // dense index (mask, fields)
   const StepShared& a = sh;
 
@@ -95,20 +39,21 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
   float f[Q], g[Q];
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
-    f[p] = pull<DS, UNIT, p>(src + p * pitch, a, nb);
-    g[p] = pull<DS, UNIT, p>(src + (Q + p) * pitch, a, nb);
+    f[p] = pull<DS, UNIT, p, p, false>(src, nb, a.tap[p]);
+    g[p] = pull<DS, UNIT, p, Q + p, false>(src, nb, a.tap[p]);
   });
 
   float Fsx = 0.0f, Fsy = 0.0f;   // stirring force, loaded with the populations
   if constexpr (FORCE == FORCE_STIR && MODE == MODE_STEP) {
-    Fsx = ld(L.force, nb.c0);
-    Fsy = ld(L.force + pitch, nb.c0);
+    const gfloat* fr = (const gfloat*)L.force + (int64_t)y * row;
+    Fsx = fr[x];
+    Fsy = fr[L.pitch + x];
   }
   // Solid nodes bounce back (F'_i = F~_opp(i)).  They run the same
   // arithmetic on a rest-frame stand-in and select at the store, so a
   // wavefront that straddles an obstacle does not diverge.
   bool solid = false;
-  if constexpr (MASK) solid = L.mask[node] != 0;
+  if constexpr (MASK) solid = ((const __attribute__((address_space(1))) uint8_t*)L.mask)[node] != 0;
 
   // 2. moments of the deviations from the reference: float32 sums over
   //    opposite pairs (even moments from f_a + f_b, odd from f_a - f_b),
@@ -178,8 +123,8 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
       atomicOr(a.err, ERR_LANDAU);
       static_for<0, Q>([&](auto P) {
         constexpr int p = decltype(P)::value;
-        st(dst + p * pitch, nb.c0, f[p]);
-        st(dst + (Q + p) * pitch, nb.c0, g[p]);
+        stp<p>(dst, nb.r[1], nb.c[1], f[p]);
+        stp<Q + p>(dst, nb.r[1], nb.c[1], g[p]);
       });
       return;
     }
@@ -242,8 +187,8 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
       if constexpr (q == p) {
         const float fn = f[p] - w0 * (f[p] - w * ec.A) - w * p0;
         const float gn = g[p] - w0 * (g[p] - w * ec.Ag);
-        st(dst + p * pitch, nb.c0, solid ? f[p] : fn);
-        st(dst + (Q + p) * pitch, nb.c0, solid ? g[p] : gn);
+        stp<p>(dst, nb.r[1], nb.c[1], solid ? f[p] : fn);
+        stp<Q + p>(dst, nb.r[1], nb.c[1], solid ? g[p] : gn);
       } else if constexpr (q > p) {
         constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
         constexpr float vxx = (float)(DS::vx[p] * DS::vx[p]);
@@ -264,10 +209,10 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
         }
         const float ga = g[p] - oa * (g[p] - (g0 + g1));
         const float gb = g[q] - ob * (g[q] - (g0 - g1));
-        st(dst + p * pitch, nb.c0, solid ? f[q] : fa);
-        st(dst + q * pitch, nb.c0, solid ? f[p] : fb);
-        st(dst + (Q + p) * pitch, nb.c0, solid ? g[q] : ga);
-        st(dst + (Q + q) * pitch, nb.c0, solid ? g[p] : gb);
+        stp<p>(dst, nb.r[1], nb.c[1], solid ? f[q] : fa);
+        stp<q>(dst, nb.r[1], nb.c[1], solid ? f[p] : fb);
+        stp<Q + p>(dst, nb.r[1], nb.c[1], solid ? g[q] : ga);
+        stp<Q + q>(dst, nb.r[1], nb.c[1], solid ? g[p] : gb);
       }
     });
   }
@@ -285,9 +230,18 @@ __global__ __launch_bounds__(64 * TY) void tile_kernel(const TileArgs a) {
     const int tile = a.tile_first + t;
     const int b = a.tile_lat ? a.tile_lat[tile] : 0;
     const LatDesc& L = a.lats[b];
+    // tiles of a lattice run strip by strip (strips a.strip tiles wide,
+    // the last one narrower), row-major inside a strip: neighbouring tiles,
+    // which share halo rows and columns, are dispatched close together
     const int lt = tile - L.tile_begin;
-    const int ty = lt / L.tiles_x;
-    const int x = (lt - ty * L.tiles_x) * 64 + lane;
+    const int tiles_y = (L.ny + TY - 1) / TY;
+    const int sw = min(a.strip, L.tiles_x);
+    const int full = L.tiles_x / sw;
+    const int st = lt / (sw * tiles_y);
+    const int w = st < full ? sw : L.tiles_x - full * sw;
+    const int in = lt - st * sw * tiles_y;
+    const int ty = in / w;
+    const int x = (st * sw + (in - ty * w)) * 64 + lane;
     const int y = __builtin_amdgcn_readfirstlane(ty * TY + row);
     if (x < L.nx && y < L.ny)
       node_update<DS, UNIT, MASK, FORCE, MODE>(a.sh, L, L.state[a.parity],
@@ -301,12 +255,11 @@ template <class DS>
 __global__ __launch_bounds__(256) void init_kernel(
     const float* __restrict__ eps, const float* __restrict__ bx,
     const float* __restrict__ by, const float* __restrict__ nn, float* dst,
-    int64_t pitch, int32_t nx, int32_t ny, int32_t row, double eps_ref, double n_ref,
+    int32_t nx, int32_t ny, int32_t row, double eps_ref, double n_ref,
     uint32_t* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nx * ny) return;
-  const int yy = i / nx;
-  const int o = yy * row + (i - yy * nx);   // padded offset of dense node i
+  const int yy = i / nx, xx = i - yy * nx;
   Frame fr;
   if (!frame_from_beta((double)eps[i], (double)bx[i], (double)by[i], fr)) {
     atomicOr(err, ERR_LANDAU);
@@ -319,8 +272,8 @@ __global__ __launch_bounds__(256) void init_kernel(
     constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
     constexpr float w = DS::w32[p];
     const float s = ux * vx + uy * vy;
-    dst[p * pitch + o] = w * (ec.A + s * (ec.B + s * ec.C));
-    dst[(DS::Q + p) * pitch + o] = w * (ec.Ag + s * ec.Bg);
+    dst[state_elem<DS::Q>(p, xx, yy, row)] = w * (ec.A + s * (ec.B + s * ec.C));
+    dst[state_elem<DS::Q>(DS::Q + p, xx, yy, row)] = w * (ec.Ag + s * ec.Bg);
   });
 }
 
@@ -390,6 +343,15 @@ int tiles_of(int nx, int ny, int tile_rows) {
   return ((nx + 63) / 64) * ((ny + tile_rows - 1) / tile_rows);
 }
 
+std::vector<LaunchShape> launch_candidates(int Q) {
+  std::vector<LaunchShape> c;
+  for (int ty : {1, 2, 4, 8})
+    for (int g : {0, 4})
+      for (int sw : {4, 8, 16, 32})
+        if (Q == 17 || ty == 4) c.push_back(LaunchShape{ty, g, sw});
+  return c;
+}
+
 template <class DS, bool UNIT, bool MASK, int FORCE, int MODE, int TY>
 static void go(const TileArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL((tile_kernel<DS, UNIT, MASK, FORCE, MODE, TY>), dim3(grid),
@@ -438,6 +400,7 @@ hipError_t launch_tiles(int Q, bool unit, bool mask, int mode, int force_mode,
   int ty = shape.tile_rows;
   if (!(Q == 17 && mode == MODE_STEP)) ty = 4;
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
+  a.strip = std::max(1, shape.strip);
   int grid;
   if (shape.grid_per_cu <= 0) {
     grid = 8 * a.tiles_per_xcd;
@@ -476,11 +439,11 @@ hipError_t launch_init(const rlb_lattice* lat, const float* eps,
   const dim3 grid((ncell + 255) / 256);
   if (lat->Q == 17)
     hipLaunchKernelGGL(init_kernel<Dir17>, grid, dim3(256), 0, lat->stream, eps,
-                       bx, by, n, dst, lat->pitch, lat->p.nx, lat->p.ny, lat->row,
+                       bx, by, n, dst, lat->p.nx, lat->p.ny, lat->row,
                        lat->p.eps_ref, lat->p.n_ref, lat->err);
   else
     hipLaunchKernelGGL(init_kernel<Dir26>, grid, dim3(256), 0, lat->stream, eps,
-                       bx, by, n, dst, lat->pitch, lat->p.nx, lat->p.ny, lat->row,
+                       bx, by, n, dst, lat->p.nx, lat->p.ny, lat->row,
                        lat->p.eps_ref, lat->p.n_ref, lat->err);
   return hipGetLastError();
 }

@@ -38,6 +38,12 @@ SYMBOLS = [
 OBJECTIVES = {"current": 0, "dissipation": 1}
 
 
+def _tune_rows(out):
+    rows = [(int(out[4 * i]), int(out[4 * i + 1]), int(out[4 * i + 2]), out[4 * i + 3])
+            for i in range(len(out) // 4)]
+    return [r for r in rows if r[3] > 0]
+
+
 class RLBError(RuntimeError):
     def __init__(self, status, message):
         self.status = status
@@ -98,8 +104,8 @@ def lib():
         "rlb_timing": [_vp, _i32],
         "rlb_timing_read": [_vp, _P(_d), _P(_i64)],
         "rlb_copy_probe": [_vp, _vp, _sz, _vp],
-        "rlb_set_launch_shape": [_vp, _i32, _i32],
-        "rlb_get_launch_shape": [_vp, _P(_i32), _P(_i32)],
+        "rlb_set_launch_shape": [_vp, _i32, _i32, _i32],
+        "rlb_get_launch_shape": [_vp, _P(_i32), _P(_i32), _P(_i32)],
         "rlb_autotune": [_vp, _i32, _P(_d), _i32],
         "rlb_batch_workspace_bytes": [_P(Params), _i32, _vp, _vp, _P(_sz)],
         "rlb_batch_create": [_P(Params), _i32, _vp, _vp, _vp, _sz, _vp, _P(_vp)],
@@ -109,8 +115,8 @@ def lib():
         "rlb_batch_step": [_vp, _i64],
         "rlb_batch_sync": [_vp],
         "rlb_batch_info": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_i64)],
-        "rlb_batch_set_launch_shape": [_vp, _i32, _i32],
-        "rlb_batch_get_launch_shape": [_vp, _P(_i32), _P(_i32)],
+        "rlb_batch_set_launch_shape": [_vp, _i32, _i32, _i32],
+        "rlb_batch_get_launch_shape": [_vp, _P(_i32), _P(_i32), _P(_i32)],
         "rlb_batch_autotune": [_vp, _i32, _P(_d), _i32],
         "rlb_batch_use_graph": [_vp, _i32],
         "rlb_batch_timing": [_vp, _i32],
@@ -299,7 +305,8 @@ class Lattice:
         return np.array(out[:])
 
     def layout(self):
-        """(planes per family, row pitch, plane pitch, header bytes)."""
+        """(planes per family, row pitch, state row stride, header bytes); see
+        rlb_layout for the node-brick addressing."""
         q, row, pitch, hb = _i32(), _i32(), _i64(), _sz()
         check(lib().rlb_layout(self._h, ctypes.byref(q), ctypes.byref(row), ctypes.byref(pitch),
                                ctypes.byref(hb)))
@@ -324,9 +331,10 @@ class Lattice:
         of shape (Q, ny, nx) holding F_i - w_i eps_ref and G_i - w_i n_ref."""
         torch = _torch()
         buf = self.save_state() if buf is None else buf
-        q, row, pitch, hb = self.layout()
-        f = buf[hb:].view(torch.float32).view(2 * q, pitch)[:, :self.ny * row]
-        f = f.reshape(2 * q, self.ny, row)[:, :, :self.nx]
+        q, row, stride, hb = self.layout()
+        f = buf[hb:hb + 4 * self.ny * stride].view(torch.float32)
+        f = f.view(self.ny, row // 64, 2 * q, 64).permute(2, 0, 1, 3).reshape(2 * q, self.ny, row)
+        f = f[:, :, :self.nx]
         return f[:q], f[q:]
 
     def stirring_coefficients(self, step):
@@ -343,21 +351,21 @@ class Lattice:
         check(lib().rlb_stirring_field(self._h, int(step), _vp(out.data_ptr())))
         return out
 
-    def set_launch_shape(self, tile_rows, grid_per_cu):
-        check(lib().rlb_set_launch_shape(self._h, int(tile_rows), int(grid_per_cu)))
+    def set_launch_shape(self, tile_rows, grid_per_cu=0, strip=16):
+        check(lib().rlb_set_launch_shape(self._h, int(tile_rows), int(grid_per_cu), int(strip)))
 
     def launch_shape(self):
-        a, b = _i32(), _i32()
-        check(lib().rlb_get_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        """(tile_rows, grid_per_cu, strip)."""
+        a, b, c = _i32(), _i32(), _i32()
+        check(lib().rlb_get_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def autotune(self, trials=5):
         """Time every launch shape on the current state (which does not
-        advance), keep the fastest; returns [(tile_rows, grid_per_cu, ms)]."""
-        out = (_d * (3 * 64))()
+        advance), keep the fastest; returns [(tile_rows, grid_per_cu, strip, ms)]."""
+        out = (_d * (4 * 64))()
         check(lib().rlb_autotune(self._h, int(trials), out, 64))
-        rows = [(int(out[3 * i]), int(out[3 * i + 1]), out[3 * i + 2]) for i in range(64)]
-        return [r for r in rows if r[2] > 0]
+        return _tune_rows(out)
 
     def timing(self, enable=True):
         check(lib().rlb_timing(self._h, 1 if enable else 0))
@@ -458,19 +466,21 @@ class Batch:
                                    ctypes.byref(st)))
         return dict(count=c.value, cells=cells.value, planes=q.value, step=st.value)
 
-    def set_launch_shape(self, tile_rows, grid_per_cu):
-        check(lib().rlb_batch_set_launch_shape(self._h, int(tile_rows), int(grid_per_cu)))
+    def set_launch_shape(self, tile_rows, grid_per_cu=0, strip=16):
+        check(lib().rlb_batch_set_launch_shape(self._h, int(tile_rows), int(grid_per_cu), int(strip)))
 
     def launch_shape(self):
-        a, b = _i32(), _i32()
-        check(lib().rlb_batch_get_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        """(tile_rows, grid_per_cu, strip)."""
+        a, b, c = _i32(), _i32(), _i32()
+        check(lib().rlb_batch_get_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b),
+                                               ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def autotune(self, trials=5):
-        out = (_d * (3 * 64))()
+        """As Lattice.autotune, for the batched step."""
+        out = (_d * (4 * 64))()
         check(lib().rlb_batch_autotune(self._h, int(trials), out, 64))
-        rows = [(int(out[3 * i]), int(out[3 * i + 1]), out[3 * i + 2]) for i in range(64)]
-        return [r for r in rows if r[2] > 0]
+        return _tune_rows(out)
 
     def use_graph(self, steps_per_graph=16):
         check(lib().rlb_batch_use_graph(self._h, int(steps_per_graph)))

@@ -50,20 +50,23 @@ def test_launch_shapes_are_bitwise_identical():
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import Lattice
     ref = None
+    # 200 columns = 4 tiles per row: strips of 1, 3 (3 + a ragged 1) and 16
     for ty in (1, 2, 4, 8):
-        for g in (0, 2, 8):
-            lat = Lattice(67, 37, 0.7, walls=True)
-            lat.set_launch_shape(ty, g)
-            f = workloads.random_fields(67, 37, seed=4)
-            lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
-            lat.add_disks([(20.0, 15.0, 5.0)])
-            lat.set_stirring(2, 5, 1e-4, 9)
-            lat.set_body_force(1e-4, 0)
-            lat.step(11)
-            s = lat.save_state().cpu()
-            if ref is None:
-                ref = s
-            assert torch.equal(s, ref), (ty, g)
+        for g in (0, 8):
+            for sw in (1, 3, 16):
+                lat = Lattice(200, 37, 0.7, walls=True)
+                lat.set_launch_shape(ty, g, sw)
+                assert lat.launch_shape() == (ty, g, sw)
+                f = workloads.random_fields(200, 37, seed=4)
+                lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+                lat.add_disks([(20.0, 15.0, 5.0), (150.0, 20.0, 4.0)])
+                lat.set_stirring(2, 5, 1e-4, 9)
+                lat.set_body_force(1e-4, 0)
+                lat.step(11)
+                s = lat.save_state().cpu()
+                if ref is None:
+                    ref = s
+                assert torch.equal(s, ref), (ty, g, sw)
 
 
 @pytest.mark.parametrize("graph", [16, 0], ids=["graph", "direct"])
@@ -104,7 +107,7 @@ def test_autotune_does_not_advance_and_keeps_results():
     B.step(3)
     before = [B[b].save_state().cpu() for b in range(len(SIZES))]
     rows = B.autotune(trials=2)
-    assert len(rows) == 16 and all(r[2] > 0 for r in rows)
+    assert len(rows) == 32 and all(r[3] > 0 for r in rows)
     after = [B[b].save_state().cpu() for b in range(len(SIZES))]
     for x, y in zip(before, after):
         assert torch.equal(x, y)
