@@ -81,7 +81,7 @@ Workspace layout(const rlb_params* p, int Q, int64_t pitch) {
   w.table_off = off; off += align_up((size_t)p->ny * (kMaxK + 1) * sizeof(float4));
   w.phase_off = off; off += align_up((size_t)p->ny * sizeof(double2));
   w.force_off = off; off += align_up((size_t)2 * pitch * sizeof(float));
-  w.twiddle_off = off; off += align_up((size_t)kMaxK * p->nx * sizeof(float2));
+  w.twiddle_off = off; off += align_up((size_t)(kMaxK + 1) * p->nx * sizeof(float2));
   w.partial_off = off; off += align_up((size_t)kRedBlocks * 4 * sizeof(double));
   w.desc_off = off; off += align_up(sizeof(LatDesc));
   w.misc_off = off; off += align_up(256);

@@ -152,7 +152,6 @@ __device__ __forceinline__ bool frame_from_beta(double eps, double bx,
   return true;
 }
 
-constexpr int kTableStride = 64;   // stirring table entries per row (|k| <= 63)
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11) and the Box-Muller transform.

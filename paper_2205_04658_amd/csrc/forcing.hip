@@ -8,11 +8,15 @@
 // shell sum along ky into the row's real trigonometric series in x,
 // a_k cos(k th) + b_k sin(k th), th = 2 pi x / nx, summing modes in a fixed
 // order; (3) the synthesis kernel evaluates the series at every node and
-// writes the two force planes the step kernel reads.  Each synthesis thread
-// owns one column, loads its cos/sin(k th) once from a static twiddle table
-// and sweeps 32 rows, so the per-node cost is 4 FMAs per k.
+// writes the two force planes the step kernel reads.  The synthesis is a
+// dense product, F_c(y, x) = sum_j A_c(y, j) T(j, x) over the 2 (K + 1)
+// slots j = (k, cos | sin), so it runs on the matrix cores: float32
+// v_mfma_f32_32x32x2f32, one k (two slots) per instruction.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "device_common.hpp"
+#include "brick.hpp"
 
 namespace rlb {
 
@@ -37,83 +41,131 @@ __global__ __launch_bounds__(256) void stir_draw_kernel(const StirArgs a,
   if (fixed_step < 0 && threadIdx.x == 0) *a.dstep = t + 1;
 }
 
-// One wavefront per row y; lane k builds the series coefficients of |kx| = k
-// from the modes of its bin:  mode (kx, ky) with coefficient c contributes
-// prod = 2 c e^{2 pi i ky y / ny} to cos(|kx| th) with Re(prod) and to
-// sin(|kx| th) with -sign(kx) Im(prod).
+// Series coefficients: the table holds, for every |kx| = k and row y,
+// (a_k, b_k) of F^x and F^y as one float4 at [k][y] (k-major, so the
+// synthesis reads 32 consecutive rows per load).  One wavefront covers 64
+// rows of one k and sums the modes of that bin in their fixed order: mode
+// (kx, ky) with coefficient c contributes prod = 2 c e^{2 pi i ky y / ny}
+// to cos(k th) with Re(prod) and to sin(k th) with -sign(kx) Im(prod).
 __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a) {
-  const int y = blockIdx.x;
-  const int k = threadIdx.x;
+  const int y = blockIdx.x * 64 + threadIdx.x;
+  const int k = blockIdx.y;   // 0 .. K rounded up to 4 (rows past K are zero)
   if (y >= a.ny) return;
-  float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (k <= a.K) {
-    double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
-    const int j1 = a.bins[k + 1];
-    for (int j = a.bins[k]; j < j1; ++j) {
-      const int4 md = a.modes[j];
-      // e^{2 pi i ky y / ny} from the phase table, index reduced exactly
-      const double2 e = a.phase[((long long)md.z * y) % a.ny];
-      const double cs = e.x, sn = e.y;
-      const double* c = a.coef + 4 * (size_t)md.x;
-      const double pxr = 2.0 * (c[0] * cs - c[1] * sn);
-      const double pxi = 2.0 * (c[0] * sn + c[1] * cs);
-      const double pyr = 2.0 * (c[2] * cs - c[3] * sn);
-      const double pyi = 2.0 * (c[2] * sn + c[3] * cs);
-      const double sg = md.y > 0 ? -1.0 : 1.0;   // kx = 0 has no sine part
-      ax += pxr;
-      bx += sg * pxi;
-      ay += pyr;
-      by += sg * pyi;
-    }
-    out = make_float4((float)ax, (float)(k ? bx : 0.0), (float)ay, (float)(k ? by : 0.0));
+  double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
+  const int j1 = k <= a.K ? a.bins[k + 1] : 0;
+  for (int j = k <= a.K ? a.bins[k] : 0; j < j1; ++j) {
+    const int4 md = a.modes[j];
+    // e^{2 pi i ky y / ny} from the phase table, index reduced exactly
+    const double2 e = a.phase[((long long)md.z * y) % a.ny];
+    const double cs = e.x, sn = e.y;
+    const double* c = a.coef + 4 * (size_t)md.x;
+    const double pxr = 2.0 * (c[0] * cs - c[1] * sn);
+    const double pxi = 2.0 * (c[0] * sn + c[1] * cs);
+    const double pyr = 2.0 * (c[2] * cs - c[3] * sn);
+    const double pyi = 2.0 * (c[2] * sn + c[3] * cs);
+    const double sg = md.y > 0 ? -1.0 : 1.0;   // kx = 0 has no sine part
+    ax += pxr;
+    bx += sg * pxi;
+    ay += pyr;
+    by += sg * pyi;
   }
-  a.table[(size_t)y * kTableStride + k] = out;
+  a.table[(size_t)k * a.ny + y] =
+      make_float4((float)ax, (float)(k ? bx : 0.0), (float)ay, (float)(k ? by : 0.0));
 }
 
-constexpr int kSynthRows = 32;
-
-// Column twiddles (cos, sin)(2 pi k x / nx), k = 1..K, table [K][nx],
-// exactly reduced; static per lattice and shell.
+// Column twiddles (cos, sin)(2 pi k x / nx) for k = 0..kMaxK, table
+// [kMaxK + 1][nx], exactly reduced; rows past K are zero (the synthesis
+// runs k up to a multiple of 4).  Static per lattice and shell.
 __global__ __launch_bounds__(256) void twiddle_kernel(float2* tw, int K, int nx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= K * nx) return;
-  const int k = i / nx + 1, x = i - (k - 1) * nx;
-  double sn, cs;
-  sincospi(2.0 * (double)(((long long)k * x) % nx) / (double)nx, &sn, &cs);
-  tw[i] = make_float2((float)cs, (float)sn);
+  if (i >= (kMaxK + 1) * nx) return;
+  const int k = i / nx, x = i - k * nx;
+  float2 v = make_float2(0.0f, 0.0f);
+  if (k <= K) {
+    double sn, cs;
+    sincospi(2.0 * (double)(((long long)k * x) % nx) / (double)nx, &sn, &cs);
+    v = make_float2((float)cs, (float)sn);
+  }
+  tw[i] = v;
 }
 
-template <int KB>
-__global__ __launch_bounds__(64) void stir_synth_kernel(const float4* __restrict__ table,
-                                                        const float2* __restrict__ tw,
-                                                        float* __restrict__ force,
-                                                        int64_t force_pitch, int K,
-                                                        int nx, int ny, int row_pitch) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y0 = blockIdx.y * kSynthRows;
-  if (x >= nx) return;
-  float c[KB], s[KB];
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kSynthBlocks = 4;                  // 32-column blocks per wavefront
+constexpr int kSynthWaveCols = 32 * kSynthBlocks;
+constexpr int kSynthWaves = 4;                   // wavefronts per workgroup
+
+// Number of k the synthesis runs: K + 1 rounded up to a multiple of 4 (<= 64).
+static inline int synth_slots(int K) { return (K + 4) & ~3; }
+
+// One wavefront: rows y0 .. y0+31, columns xw .. xw+127, both components.
+// For each k the A operand holds the rows' (a_k, b_k) -- lanes 0-31 the cos
+// coefficient of row y0 + lane, lanes 32-63 the sin coefficient -- and the
+// B operand the columns' (cos, sin)(k th) in the same split, so one 32x32x2
+// product adds a_k cos(k th) + b_k sin(k th) to a 32 x 32 block.
+// Accumulator element i of lane l is block row 8 (i / 4) + 4 (l / 32) +
+// i % 4, column l % 32.  Both tables are zero past K, so the k loop is
+// loads and products only.  Rows and columns past the lattice are clamped
+// on load and skipped on store.
+__global__ __launch_bounds__(64 * kSynthWaves) void stir_synth_kernel(
+    const float4* __restrict__ table, const float2* __restrict__ tw, float* __restrict__ force,
+    int64_t force_pitch, int kslots, int nx, int ny, int row_pitch) {
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int tiles_x = (nx + kSynthWaveCols - 1) / kSynthWaveCols;
+  const int tile = blockIdx.x * kSynthWaves + (threadIdx.x >> 6);
+  const int ty = tile / tiles_x;
+  const int y0 = ty * 32;
+  const int xw = (tile - ty * tiles_x) * kSynthWaveCols;
+  if (y0 >= ny) return;   // wave-uniform
+  // Each lane loads only its half: component `half` of every coefficient
+  // pair and of every float2 twiddle (cos or sin), as a wave-uniform base
+  // (the k row) plus a per-lane 32-bit offset (row or column).
+  const uint32_t ao = 16u * (uint32_t)min(y0 + l32, ny - 1) + 4u * half;
+  uint32_t bo[kSynthBlocks];
 #pragma unroll
-  for (int k = 1; k <= KB; ++k) {
-    float2 t = make_float2(0.0f, 0.0f);
-    if (k <= K) t = tw[(size_t)(k - 1) * nx + x];
-    c[k - 1] = t.x;
-    s[k - 1] = t.y;
+  for (int b = 0; b < kSynthBlocks; ++b)
+    bo[b] = 8u * (uint32_t)min(xw + 32 * b + l32, nx - 1) + 4u * half;
+  floatx16 acc[2][kSynthBlocks];
+#pragma unroll
+  for (int b = 0; b < kSynthBlocks; ++b) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) { acc[0][b][i] = 0.0f; acc[1][b][i] = 0.0f; }
   }
-  const int y1 = min(y0 + kSynthRows, ny);
-  for (int y = y0; y < y1; ++y) {
-    // the row's coefficients are wave-uniform: scalar loads
-    const float4* __restrict__ row = table + (size_t)y * kTableStride;
-    float4 t = row[0];
-    float fx = t.x, fy = t.z;
+  for (int k0 = 0; k0 < kslots; k0 += 4) {
+    float ax[4], ay[4], bv[4][kSynthBlocks];
 #pragma unroll
-    for (int k = 1; k <= KB; ++k) {
-      t = row[k];   // zero beyond K
-      fx += t.x * c[k - 1] + t.y * s[k - 1];
-      fy += t.z * c[k - 1] + t.w * s[k - 1];
+    for (int j = 0; j < 4; ++j) {
+      const gbyte* ak = (const gbyte*)(table + (size_t)(k0 + j) * ny);
+      ax[j] = *(const gfloat*)(ak + ao);
+      ay[j] = *(const gfloat*)(ak + ao + 8);
+      const gbyte* tk = (const gbyte*)(tw + (size_t)(k0 + j) * nx);
+#pragma unroll
+      for (int b = 0; b < kSynthBlocks; ++b) bv[j][b] = *(const gfloat*)(tk + bo[b]);
     }
-    force[(size_t)y * row_pitch + x] = fx;
-    force[force_pitch + (size_t)y * row_pitch + x] = fy;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int b = 0; b < kSynthBlocks; ++b) {
+        acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ax[j], bv[j][b], acc[0][b], 0, 0, 0);
+        acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ay[j], bv[j][b], acc[1][b], 0, 0, 0);
+      }
+    }
+  }
+  // store block by block (the barriers keep one block's accumulators in
+  // flight to memory at a time)
+#pragma unroll
+  for (int b = 0; b < kSynthBlocks; ++b) {
+    const int x = xw + 32 * b + l32;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int y = y0 + 8 * (i >> 2) + 4 * half + (i & 3);
+      if (x < nx && y < ny) {
+        force[(size_t)y * row_pitch + x] = acc[0][b][i];
+        force[force_pitch + (size_t)y * row_pitch + x] = acc[1][b][i];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -148,29 +200,20 @@ hipError_t launch_stir_draw(const StirArgs& a, int64_t fixed_step,
 }
 
 hipError_t launch_stir_table(const StirArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(stir_table_kernel, dim3(a.ny), dim3(kTableStride), 0, s, a);
+  hipLaunchKernelGGL(stir_table_kernel, dim3((a.ny + 63) / 64, synth_slots(a.K)), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s) {
-  const dim3 grid((a.nx + 63) / 64, (a.ny + kSynthRows - 1) / kSynthRows);
-  const float4* t = a.table;
-#define RLB_SYNTH(KB)                                                                  \
-  hipLaunchKernelGGL(stir_synth_kernel<KB>, grid, dim3(64), 0, s, t, a.twiddle, a.force,     \
-                     a.force_pitch, a.K, a.nx, a.ny, a.row)
-  if (a.K <= 8) RLB_SYNTH(8);
-  else if (a.K <= 16) RLB_SYNTH(16);
-  else if (a.K <= 24) RLB_SYNTH(24);
-  else if (a.K <= 34) RLB_SYNTH(34);
-  else if (a.K <= 48) RLB_SYNTH(48);
-  else RLB_SYNTH(63);
-#undef RLB_SYNTH
+  const int tiles = ((a.nx + kSynthWaveCols - 1) / kSynthWaveCols) * ((a.ny + 31) / 32);
+  hipLaunchKernelGGL(stir_synth_kernel, dim3((tiles + kSynthWaves - 1) / kSynthWaves),
+                     dim3(64 * kSynthWaves), 0, s, a.table, a.twiddle, a.force, a.force_pitch,
+                     synth_slots(a.K), a.nx, a.ny, a.row);
   return hipGetLastError();
 }
 
 hipError_t launch_twiddle(float2* tw, int K, int nx, hipStream_t s) {
-  if (K <= 0) return hipSuccess;
-  hipLaunchKernelGGL(twiddle_kernel, dim3((K * nx + 255) / 256), dim3(256), 0, s, tw, K, nx);
+  hipLaunchKernelGGL(twiddle_kernel, dim3(((kMaxK + 1) * nx + 255) / 256), dim3(256), 0, s, tw, K, nx);
   return hipGetLastError();
 }
 

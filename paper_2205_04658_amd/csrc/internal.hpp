@@ -82,9 +82,9 @@ struct StirArgs {
   const int4* modes;      // binned list (m, kx, ky, 0), grouped by |kx|
   const int32_t* bins;    // [K+2] offsets of |kx| = 0..K in `modes`
   double* coef;           // [nmodes][4] (Re Fx, Im Fx, Re Fy, Im Fy)
-  float4* table;          // [ny][kMaxK+1]
+  float4* table;          // [kMaxK+1][ny] series coefficients (a_k, b_k) of F^x, F^y
   const double2* phase;   // [ny] (cos, sin)(2 pi m / ny)
-  const float2* twiddle;  // [K][nx] (cos, sin)(2 pi k x / nx)
+  const float2* twiddle;  // [kMaxK+1][nx] (cos, sin)(2 pi k x / nx), zero past K
   float* force;           // [2][force_pitch] synthesised force planes, rows padded
   int64_t force_pitch;
   int32_t row;
