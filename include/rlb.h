@@ -316,8 +316,22 @@ typedef struct {
   double body_force;       /* F_b                                              */
 } rlb_adjoint_cfg;
 
-/* Set the relaxation time (tau > 1/2) of an existing lattice. */
+/* Set the relaxation time (tau > 1/2) of an existing lattice; this also
+ * returns a lattice set by rlb_set_relaxation_eta_s to a constant tau.
+ * RLB_EINVAL for batch members (they share the batch's tau). */
 rlb_status rlb_set_relaxation_time(rlb_lattice* lat, double tau);
+
+/* Per-node relaxation time from a fixed shear viscosity to entropy ratio
+ * (Ch. 3, "Relativistic Lattice Boltzmann": tau_R = 5 (eta/s) / T, and
+ * "Boltzmann to Lattice Boltzmann": eps = 3 T^4 / pi^2 in natural units):
+ * each fluid node relaxes with tau(x) = 5 (eta/s) / (T(x) dt), steps,
+ * T(x) = (pi^2 eps(x) / 3)^(1/4) from its Landau energy density, dt the
+ * time step in the units of T^-1.  Stability needs tau(x) > 1/2, i.e.
+ * eps(x) < (3 / pi^2) (10 (eta/s) / dt)^4; the library does not clamp.
+ * Applies to rlb_step of single lattices; rlb_adjoint_run rejects it
+ * (RLB_EUNSUPPORTED).  RLB_EINVAL for non-positive or non-finite arguments
+ * and for batch members. */
+rlb_status rlb_set_relaxation_eta_s(rlb_lattice* lat, double eta_over_s, double dt);
 
 /* Bytes of the adjoint workspace: ceil(N/K) checkpoints + K segment states
  * + 2 adjoint states + float64 per-node accumulators. */

@@ -189,8 +189,31 @@ def equilibrium_G(n, u):
 # Collision (Ch. 3, eq. boltzmanneq_rel: Anderson-Witting rate p.u / tau_R)
 # --------------------------------------------------------------------------
 def collision_rate(u, tau):
-    """omega_i = p^mu u_mu / (p^0 tau) = (u^0 - u . v_i) / tau."""
+    """omega_i = p^mu u_mu / (p^0 tau) = (u^0 - u . v_i) / tau; tau is a
+    number or an (Ny, Nx) array (per-node relaxation time)."""
     return np.einsum("im,m,myx->iyx", VMU, np.diag(METRIC), u) / tau
+
+
+def temperature(eps):
+    """T from the massless ideal-gas energy density eps = 3 T^4 / pi^2
+    (Ch. 3, "Boltzmann to Lattice Boltzmann", natural units)."""
+    return (np.pi ** 2 * np.asarray(eps, np.float64) / 3.0) ** 0.25
+
+
+class ViscosityRelaxation:
+    """Per-node relaxation time from a fixed eta/s (Ch. 3, "Relativistic
+    Lattice Boltzmann"): tau_R = 5 (eta/s) / T, in steps of length dt,
+        tau(x) = 5 (eta/s) / (T(x) dt),
+    with T(x) from the node's Landau energy density.  Passed to `step` in
+    place of a constant tau."""
+
+    def __init__(self, eta_s, dt):
+        if not (eta_s > 0 and dt > 0):
+            raise ValueError("eta/s and dt must be positive")
+        self.eta_s, self.dt = float(eta_s), float(dt)
+
+    def __call__(self, eps):
+        return 5.0 * self.eta_s / (temperature(eps) * self.dt)
 
 
 # --------------------------------------------------------------------------
@@ -231,6 +254,8 @@ def step(F, G, tau, cfl=1.0, force=None, solid=None, collision="aw"):
       chosen so the flow accelerates along +F.
     * collision="bgk" replaces omega_i by 1/tau (the classical rate of
       Ch. 3 eq. lbe_coll_term); used only as a negative control.
+    * tau: a constant, or a ViscosityRelaxation giving tau(x) from the
+      node's Landau energy density.
     """
     Ft = stream(F, cfl)
     Gt = stream(G, cfl)
@@ -240,10 +265,13 @@ def step(F, G, tau, cfl=1.0, force=None, solid=None, collision="aw"):
     n = charge_density(J, u)
     Feq = equilibrium_F(eps, u)
     Geq = equilibrium_G(n, u)
+    if callable(tau):
+        e = eps if solid is None else np.where(solid, 1.0, eps)   # solid nodes do not collide
+        tau = tau(e)
     if collision == "aw":
         om = collision_rate(u, tau)
     elif collision == "bgk":
-        om = np.full_like(Ft, 1.0 / tau)
+        om = np.broadcast_to(1.0 / tau, Ft.shape)
     else:
         raise ValueError(collision)
     Fn = Ft - om * (Ft - Feq)

@@ -46,6 +46,8 @@ struct AdjLayout {
 rlb_status check_cfg(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
   if (!lat) return afail(RLB_EINVAL, "lattice is null");
   if (!c) return afail(RLB_EINVAL, "config is null");
+  if (lat->tau_k > 0.0)
+    return afail(RLB_EUNSUPPORTED, "the adjoint needs a constant relaxation time (rlb_set_relaxation_time)");
   if (c->nsteps < 2 || (c->nsteps & 1)) return afail(RLB_EINVAL, "nsteps must be even and >= 2");
   if (c->checkpoint < 1) return afail(RLB_EINVAL, "checkpoint interval must be >= 1");
   if (c->objective != RLB_OBJ_CURRENT && c->objective != RLB_OBJ_DISSIPATION)
@@ -91,8 +93,21 @@ extern "C" {
 
 rlb_status rlb_set_relaxation_time(rlb_lattice* lat, double tau) {
   if (!lat) return afail(RLB_EINVAL, "lattice is null");
+  if (lat->owner) return afail(RLB_EINVAL, "lattice is a batch member: members share the batch's tau");
   if (!std::isfinite(tau) || !(tau > 0.5)) return afail(RLB_EINVAL, "tau must be finite and > 1/2");
   lat->p.tau = tau;
+  lat->tau_k = 0.0;
+  return RLB_OK;
+}
+
+rlb_status rlb_set_relaxation_eta_s(rlb_lattice* lat, double eta_over_s, double dt) {
+  if (!lat) return afail(RLB_EINVAL, "lattice is null");
+  if (lat->owner) return afail(RLB_EINVAL, "lattice is a batch member: members share the batch's tau");
+  if (!std::isfinite(eta_over_s) || !(eta_over_s > 0.0) || !std::isfinite(dt) || !(dt > 0.0))
+    return afail(RLB_EINVAL, "eta/s and dt must be finite and > 0");
+  // 1/tau = dt T / (5 eta/s), T = (pi^2 eps / 3)^(1/4)
+  const double pi = 3.14159265358979323846;
+  lat->tau_k = dt * std::pow(pi * pi / 3.0, 0.25) / (5.0 * eta_over_s);
   return RLB_OK;
 }
 

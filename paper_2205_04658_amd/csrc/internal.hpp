@@ -34,7 +34,8 @@ enum ForceMode : int { FORCE_NONE = 0, FORCE_BODY = 1, FORCE_STIR = 2 };
 // Parameters shared by every lattice of one step launch.
 struct StepShared {
   float tap[kMaxQ][4];    // bilinear weights (w00, w10, w01, w11) per plane
-  float inv_tau;
+  float inv_tau;           // constant 1/tau (tau_k == 0)
+  double tau_k;            // > 0: per-node 1/tau = tau_k * eps^(1/4) (eta/s relaxation)
   double eps_ref, n_ref;
   float fx, fy;           // uniform body force
   uint32_t* err;          // sticky device error word
@@ -158,6 +159,7 @@ struct rlb_lattice {
   double* result;
   // forcing
   double fx, fy;
+  double tau_k;           // per-node relaxation from eta/s (0 = constant tau)
   bool stir;
   double kmin, kmax, amp;
   uint64_t seed;

@@ -132,7 +132,10 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
     // 4. equilibrium and collision-rate coefficients
     const EqCoef ec = eq_coef(fr, n, a.eps_ref, a.n_ref, DS::kappa);
     const float ux = (float)fr.ux, uy = (float)fr.uy;
-    const float w0 = (float)fr.u0 * a.inv_tau;
+    // 1/tau: constant, or from eta/s at the node's temperature,
+    // T ~ eps^(1/4) (tau_R = 5 (eta/s) / T with eps = 3 T^4 / pi^2)
+    const float itau = a.tau_k > 0.0 ? (float)(a.tau_k * sqrt(sqrt(fr.eps))) : a.inv_tau;
+    const float w0 = (float)fr.u0 * itau;
 
     // 5. driving term Phi(v) = p0 + px vx + py vy + pxx vx^2 + pxy vx vy
     //    + pyy vy^2 (vz^2 = 1 - vx^2 - vy^2 folded in)
@@ -195,7 +198,7 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
         constexpr float vyy = (float)(DS::vy[p] * DS::vy[p]);
         constexpr float vxy = (float)(DS::vx[p] * DS::vy[p]);
         const float s = ux * vx + uy * vy;
-        const float t = s * a.inv_tau;
+        const float t = s * itau;
         const float e0 = w * (ec.A + ec.C * s * s), e1 = w * (ec.B * s);
         const float g0 = w * ec.Ag, g1 = w * (ec.Bg * s);
         const float oa = w0 - t, ob = w0 + t;
@@ -330,6 +333,7 @@ StepShared shared_of(const rlb_lattice* lat) {
   for (int p = 0; p < kMaxQ; ++p)
     for (int c = 0; c < 4; ++c) a.tap[p][c] = lat->tap[p][c];
   a.inv_tau = (float)(1.0 / lat->p.tau);
+  a.tau_k = lat->tau_k;
   a.eps_ref = lat->p.eps_ref;
   a.n_ref = lat->p.n_ref;
   a.fx = (float)lat->fx;

@@ -33,7 +33,8 @@ SYMBOLS = [
     "rlb_batch_set_body_force", "rlb_batch_step", "rlb_batch_sync", "rlb_batch_info",
     "rlb_batch_set_launch_shape", "rlb_batch_get_launch_shape", "rlb_batch_autotune",
     "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
-    "rlb_set_relaxation_time", "rlb_adjoint_workspace_bytes", "rlb_adjoint_run",
+    "rlb_set_relaxation_time", "rlb_set_relaxation_eta_s", "rlb_adjoint_workspace_bytes",
+    "rlb_adjoint_run",
 ]
 OBJECTIVES = {"current": 0, "dissipation": 1}
 
@@ -122,6 +123,7 @@ def lib():
         "rlb_batch_timing": [_vp, _i32],
         "rlb_batch_timing_read": [_vp, _P(_d), _P(_i64)],
         "rlb_set_relaxation_time": [_vp, _d],
+        "rlb_set_relaxation_eta_s": [_vp, _d, _d],
         "rlb_adjoint_workspace_bytes": [_vp, _P(AdjointCfg), _P(_sz)],
         "rlb_adjoint_run": [_vp, _P(AdjointCfg), _vp, _sz, _P(_d), _vp],
     }
@@ -377,6 +379,10 @@ class Lattice:
 
     def set_relaxation_time(self, tau):
         check(lib().rlb_set_relaxation_time(self._h, float(tau)))
+
+    def set_relaxation_eta_s(self, eta_over_s, dt):
+        """Per-node tau(x) = 5 (eta/s) / (T(x) dt), T = (pi^2 eps / 3)^(1/4)."""
+        check(lib().rlb_set_relaxation_eta_s(self._h, float(eta_over_s), float(dt)))
 
     def adjoint_run(self, nsteps, checkpoint, objective, modes, amps, body_force, grad=True):
         """Run nsteps from the current state with F = F_b x_hat + sum_m A_m

@@ -79,3 +79,28 @@ def test_autograd_function():
     Jr, gr = lat2.adjoint_run(N, 7, "current", MODES, AMPS, FB)
     assert float(J) == Jr
     np.testing.assert_array_equal(theta.grad.numpy(), gr)
+
+
+def test_eta_s_relaxation_is_rejected_by_the_adjoint():
+    """The adjoint differentiates a constant tau; a lattice relaxing with
+    per-node tau from eta/s is refused (and accepted again after a constant
+    tau is set), and batch members cannot set their own relaxation."""
+    need_gpu()
+    from paper_2205_04658_amd.rlb import Batch, EINVAL, EUNSUPPORTED, RLBError
+    lat = gpu_lattice()
+    lat.set_relaxation_eta_s(0.02, 0.05)
+    with pytest.raises(RLBError) as e:
+        lat.adjoint_run(N, 10, "current", MODES, AMPS, FB)
+    assert e.value.status == EUNSUPPORTED
+    with pytest.raises(RLBError) as e:
+        lat.set_relaxation_eta_s(0.0, 0.05)
+    assert e.value.status == EINVAL
+    lat.set_relaxation_time(TAU)
+    J, g = lat.adjoint_run(N, 10, "current", MODES, AMPS, FB)
+    assert np.isfinite(J) and np.all(np.isfinite(g))
+    B = Batch([(64, 16), (80, 24)], 0.8)
+    for call in (lambda: B[0].set_relaxation_eta_s(0.02, 0.05), lambda: B[1].set_relaxation_time(0.9)):
+        with pytest.raises(RLBError) as e:
+            call()
+        assert e.value.status == EINVAL
+    B.close()

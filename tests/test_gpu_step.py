@@ -76,6 +76,10 @@ CASES = {
     "stirring": dict(stir=(2.0, 4.5, 2e-4, 11)),
     "walls_discs": dict(walls=True, discs=[(20.5, 17.0, 6.0), (60.2, 25.7, 4.0)], body=(1e-4, 0.0)),
     "cfl_half_walls": dict(cfl=0.5, walls=True, discs=[(5.0, 5.0, 3.0)], stir=(1.0, 3.0, 1e-4, 5)),
+    # per-node tau from eta/s (tau ~ 1.49 and ~ 0.93 at eps = 1)
+    "eta_s": dict(eta_s=(0.02, 0.05)),
+    "eta_s_walls_force": dict(eta_s=(0.01, 0.04), walls=True, discs=[(30.0, 20.0, 5.0)],
+                              body=(1e-4, 5e-5), stir=(2.0, 4.5, 1e-4, 3)),
 }
 
 
@@ -100,9 +104,13 @@ def test_step_parity(case, full):
     stir = c.get("stir")
     if stir:
         lat.set_stirring(*stir)
+    tau_o = tau
+    if c.get("eta_s"):
+        lat.set_relaxation_eta_s(*c["eta_s"])
+        tau_o = rlb.ViscosityRelaxation(*c["eta_s"])
     lat.step(steps)
     lat.sync()
-    F, G = oracle_run(f, steps, tau, cfl=cfl, solid=solid, body=body, stir=stir)
+    F, G = oracle_run(f, steps, tau_o, cfl=cfl, solid=solid, body=body, stir=stir)
     g = lat.fields()
     o = rlb.fields(F, G, cfl=cfl, solid=solid)
     err = compare(g, o, scales(beta=0.05))
