@@ -36,3 +36,28 @@ def vorticity(bx, by):
 def enstrophy(bx, by):
     """Z = sum over nodes of omega^2."""
     return float((vorticity(bx, by) ** 2).sum())
+
+
+# --------------------------------------------------------------------------
+# Current-density fluctuations (Ch. 6, "Model and Methods": j(t) at the
+# outflow border, j(x) along the sampling region, and their spectra)
+# --------------------------------------------------------------------------
+def column_current(fields, x):
+    """j at column x: the charge current J^x averaged over the column's
+    nodes (solid nodes count as zero), from a dict of fields."""
+    return float(np.mean(fields["Jx"][:, x]))
+
+
+def power_spectrum(series):
+    """One-sided power spectrum of the fluctuations of a real series s of
+    length n: P(k) = |sum_t (s_t - mean s) exp(-2 pi i k t / n)|^2 / n^2 for
+    k = 0 .. n // 2, evaluated as the plain sum (no FFT)."""
+    s = np.asarray(series, np.float64)
+    n = s.size
+    d = s - s.mean()
+    t = np.arange(n)
+    out = np.empty(n // 2 + 1)
+    for k in range(n // 2 + 1):
+        ph = 2.0 * np.pi * ((k * t) % n) / n
+        out[k] = (np.dot(d, np.cos(ph)) ** 2 + np.dot(d, np.sin(ph)) ** 2) / float(n) ** 2
+    return out

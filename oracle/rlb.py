@@ -42,7 +42,8 @@ def stream(F, cfl=1.0):
     set is off-lattice, so the value arriving at node x is the bilinear
     interpolation of the pre-stream field at the departure point x - delta_i.
     The lattice has one z node, so the z displacement is the identity.
-    Borders are periodic in x and y (walls are solid nodes, see `step`).
+    Borders are periodic in x and y (walls are solid nodes, and open x
+    borders overwrite their columns after the update, see `step`).
     """
     if not (0.0 < cfl <= 1.0):
         raise ValueError("bilinear pull needs 0 < cfl <= 1")
@@ -242,7 +243,7 @@ def driving_term(Ft, force):
 # --------------------------------------------------------------------------
 # The full step
 # --------------------------------------------------------------------------
-def step(F, G, tau, cfl=1.0, force=None, solid=None, collision="aw"):
+def step(F, G, tau, cfl=1.0, force=None, solid=None, collision="aw", open_x=None):
     """One time step: stream, (bounce-back), moments, Landau, equilibrium,
     collide and drive.  Returns the post-collision (F, G).
 
@@ -256,6 +257,9 @@ def step(F, G, tau, cfl=1.0, force=None, solid=None, collision="aw"):
       Ch. 3 eq. lbe_coll_term); used only as a negative control.
     * tau: a constant, or a ViscosityRelaxation giving tau(x) from the
       node's Landau energy density.
+    * open_x = (beta_x, beta_y, n_in, eps_out): open x borders (Ch. 6
+      "Model and Methods": a fixed velocity enters along the inflow border,
+      the lateral borders are periodic); see `open_borders`.
     """
     Ft = stream(F, cfl)
     Gt = stream(G, cfl)
@@ -281,7 +285,36 @@ def step(F, G, tau, cfl=1.0, force=None, solid=None, collision="aw"):
     if solid is not None:
         Fn[:, solid] = Ft[OPP][:, solid]
         Gn[:, solid] = Gt[OPP][:, solid]
+    if open_x is not None:
+        open_borders(Fn, Gn, *open_x)
     return Fn, Gn
+
+
+def open_borders(F, G, bx, by, n_in, eps_out):
+    """Open x borders, applied in place to a post-collision state:
+
+    * velocity inlet, column x = 0: F_eq, G_eq at the prescribed 3-velocity
+      (bx, by) and charge density n_in, with the energy density of the
+      adjacent column x = 1;
+    * pressure outlet, column x = Nx-1: F_eq, G_eq at the prescribed energy
+      density eps_out (pressure eps_out / 3), with the velocity and charge
+      density of the adjacent column x = Nx-2.
+
+    The adjacent columns' eps, u and n come from Landau matching of their
+    (post-collision) moments.  Streaming stays periodic: the wrapped values
+    only ever reach the two border columns, which this overwrites."""
+    ny = F.shape[1]
+    T1 = energy_momentum(F[:, :, 1:2])
+    e1, _ = landau(T1)
+    u_in = four_velocity_from_beta(np.full((ny, 1), float(bx)), np.full((ny, 1), float(by)))
+    F[:, :, 0] = equilibrium_F(e1, u_in)[:, :, 0]
+    G[:, :, 0] = equilibrium_G(np.full((ny, 1), float(n_in)), u_in)[:, :, 0]
+    Tm = energy_momentum(F[:, :, -2:-1])
+    Jm = charge_current(G[:, :, -2:-1])
+    _, um = landau(Tm)
+    nm = charge_density(Jm, um)
+    F[:, :, -1] = equilibrium_F(np.full((ny, 1), float(eps_out)), um)[:, :, 0]
+    G[:, :, -1] = equilibrium_G(nm, um)[:, :, 0]
 
 
 def initial_state(eps, bx, by, n):
