@@ -110,13 +110,15 @@ print(json.dumps(dict(steps=steps, seconds=el, cells=n * n)))
                       f"{d['steps']} steps in {d['seconds']:.1f} s, float64 NumPy, 1 thread"}
 
 
-def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None):
+def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=None):
     c = workloads.FORCED_4096
     nx, ny = c["nx"], c["ny"]
     lat = rlb.Lattice(nx, ny, c["tau"], full26=(layout == "full26"), eps_ref=c["eps"], n_ref=c["n"])
     f = workloads.uniform(nx, ny, c["eps"], c["n"])
     lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
     lat.set_stirring(c["kmin"], c["kmax"], c["amplitude"], c["seed"])
+    if eta_s is not None:                  # per-node tau from eta/s instead of tau
+        lat.set_relaxation_eta_s(*eta_s)
     lat.step(2)
     if shape is None:
         tune = lat.autotune(trials=5)      # keeps the fastest launch shape
@@ -193,6 +195,59 @@ def run_batch(torch, rlb, workloads, steps, warmup):
     return out
 
 
+def run_part2(torch, rlb, workloads, steps=2000, warmup=100):
+    """The Part II channel: 1024 x 256, velocity inlet at 0.1 (v_F = 1),
+    pressure outlet, periodic lateral borders, two impurities of diameter
+    0.5 um (radius 6.58 nodes) 3.38 um apart, tau 0.6, started from the
+    uniform inflow state.  Two timings of the
+    same run: steps alone, and steps with the per-step j(t) sample at the
+    column before the outlet (the workload's diagnostic).  j(omega) of the
+    recorded series is computed once at the end (timed separately)."""
+    c = workloads.PART2
+    nx, ny = c["nx"], c["ny"]
+    lat = rlb.Lattice(nx, ny, c["tau"], open_x=True, eps_ref=c["eps"], n_ref=c["n"])
+    f = workloads.uniform(nx, ny, c["eps"], c["n"])
+    f["bx"][:] = c["beta_in"]
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    lat.add_disks(np.array(workloads.part2_discs(3.38)))
+    lat.set_open_borders(c["beta_in"], 0.0, c["n"], c["eps_out"])
+    lat.step(2)
+    tune = lat.autotune(trials=5)
+    lat.step(warmup)
+    lat.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, kn = lat.timing_read()
+    series = torch.zeros(steps, dtype=torch.float64, device=lat.device)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for t in range(steps):
+        lat.step(1)
+        lat.column_current(nx - 2, out=series[t:t + 1])
+    torch.cuda.synchronize()
+    wall_j = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    spec = rlb.power_spectrum(series)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t2
+    lat.sync()
+    out = dict(workload="channel 1024x256, inlet beta 0.1, pressure outlet, periodic y, two discs "
+                        "d=0.5um (r=6.58) 3.38um apart, tau 0.6, started from the inflow state",
+               steps=steps, mlups=nx * ny * steps / wall / 1e6, ms_per_step=wall / steps * 1e3,
+               kernel_ms=kms / max(kn, 1), bytes_per_cell=2 * 2 * lat.layout()[0] * 4 + 1,
+               mlups_with_j=nx * ny * steps / wall_j / 1e6, spectrum_ms=wall_s * 1e3,
+               j_mean=float(series.mean()), j_peak_bin=int(spec[1:].argmax()) + 1,
+               shape=lat.launch_shape())
+    out["achieved_gbs"] = out["bytes_per_cell"] * nx * ny / (out["kernel_ms"] * 1e-3) / 1e9
+    out["hbm_frac"] = out["achieved_gbs"] / HBM_PEAK_GBS
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_adjoint(torch, rlb, workloads):
     """The gradient workload: 512 x 256 channel, walls, discs of radius 6 at
     5 % area (seed 7), tau 0.8, F = 1e-6 x_hat + 32 basis modes (7 <= |k| <=
@@ -245,6 +300,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-part2", action="store_true")
     ap.add_argument("--shape", default=None,
                     help="tile_rows,grid_per_cu,strip: fixed launch shape instead of the autotuner")
     a = ap.parse_args()
@@ -264,10 +320,19 @@ def main():
         variants[other] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms", "bytes_per_cell",
                                              "achieved_gbs")}
         variants[other]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
+        # per-node tau from eta/s (eta/s = 0.007, dt = 0.05: tau = 0.52 at eps = 1)
+        v = run_plain(torch, rlb, workloads, a.layout, max(a.steps // 3, 10), a.warmup,
+                      eta_s=(0.007, 0.05))
+        variants["eta_s"] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms", "bytes_per_cell",
+                                               "achieved_gbs")}
+        variants["eta_s"]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
     batched = None
     if not a.no_batch:
         batched = run_batch(torch, rlb, workloads, max(a.steps // 5, 50), 20)
         batched["vs_plain"] = batched["mlups"] / main_run["mlups"]
+    part2 = None
+    if not a.no_part2:
+        part2 = run_part2(torch, rlb, workloads)
     adjoint = None
     if not a.no_adjoint:
         adjoint = run_adjoint(torch, rlb, workloads)
@@ -294,6 +359,7 @@ def main():
         "copy_probe_gbs": copy_gbs,
         "batched": batched,
         "adjoint": adjoint,
+        "part2_channel": part2,
         "variants": variants,
         "cpu_baseline": cpu,
     }

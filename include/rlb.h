@@ -56,6 +56,8 @@ typedef enum {
 #define RLB_WALLS_Y 0x1u  /* rows y = 0 and y = ny-1 are solid (channel)      */
 #define RLB_FULL26  0x2u  /* store all 26 populations per family instead of  */
                           /* the 17 z-mirror-folded planes (see rlb_create)   */
+#define RLB_OPEN_X  0x4u  /* open x borders: velocity inlet at x = 0,        */
+                          /* pressure outlet at x = nx-1 (rlb_set_open_borders) */
 
 /* Lattice parameters.
  *   nx, ny   lattice nodes (one z node); 4 <= nx, ny; ny * (nx rounded up
@@ -64,7 +66,7 @@ typedef enum {
  *            tau_R (eps + P) / 5; the scheme's shear viscosity is
  *            (tau - 1/2)/5 + nu_interp).
  *   cfl      dt/dx in (0, 1]; populations move cfl * (v_x, v_y) per step.
- *   flags    RLB_WALLS_Y | RLB_FULL26.
+ *   flags    RLB_WALLS_Y | RLB_FULL26 | RLB_OPEN_X.
  *   eps_ref, n_ref  shifted-storage references: populations are stored as
  *            F_i - w_i eps_ref and G_i - w_i n_ref in float32 (the float32
  *            rounding then acts on the deviation only).  Any finite value is
@@ -187,6 +189,38 @@ rlb_status rlb_load_state(rlb_lattice* lat, const void* d_buf, size_t bytes);
  * planes together, 256 bytes per plane. */
 rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitch,
                       int64_t* row_stride, size_t* header_bytes);
+
+/* Open x borders of a lattice created with RLB_OPEN_X (Ch. 6, "Model and
+ * Methods": a fixed velocity enters along the inflow border, the lateral
+ * borders are periodic).  After every step:
+ *   - velocity inlet, column x = 0: equilibrium at 3-velocity (bx, by) and
+ *     charge density n_in, with the energy density of column 1;
+ *   - pressure outlet, column x = nx-1: equilibrium at energy density
+ *     eps_out (pressure eps_out / 3), with the velocity and charge density
+ *     of column nx-2;
+ * the adjacent columns' eps, u, n from Landau matching of their stored
+ * moments.  Streaming stays periodic (the wrapped values only reach the
+ * border columns, which are overwritten), so fields read at x = 0 and
+ * x = nx-1 mix the two borders.  Defaults at creation: beta = 0,
+ * n_in = n_ref, eps_out = eps_ref.  RLB_EINVAL without RLB_OPEN_X, for
+ * |beta| >= 1, non-finite n_in or eps_out <= 0.  Not supported in batches or
+ * by rlb_adjoint_run (RLB_EUNSUPPORTED). */
+rlb_status rlb_set_open_borders(rlb_lattice* lat, double bx, double by, double n_in,
+                                double eps_out);
+
+/* Current density at column x (Ch. 6: j recorded at the outflow border and
+ * along the channel): d_out[0] = (1/ny) sum_y J^x(x, y) of the current step
+ * (streamed populations, as rlb_read_fields; solid nodes count as zero),
+ * float64, written asynchronously on the lattice stream.  Collect a time
+ * series by passing d_out + t at successive steps. */
+rlb_status rlb_column_current(rlb_lattice* lat, int32_t x, double* d_out);
+
+/* One-sided power spectrum of the fluctuations of a float64 device series
+ * s[0..n), 2 <= n <= 2^26: d_out[k] = |sum_t (s_t - mean) e^{-2 pi i k t/n}|^2
+ * / n^2 for k = 0 .. n/2 (n/2 + 1 doubles; a plain sum, angles reduced
+ * exactly), on hip_stream.  j(omega) from a j(t) series, j(k_x) from a j(x)
+ * line.  d_out must not overlap d_series. */
+rlb_status rlb_power_spectrum(const double* d_series, int64_t n, double* d_out, void* hip_stream);
 
 /* Stirring coefficients of a given step without advancing anything:
  * d_out[4m .. 4m+3] = (Re Fx_hat, Im Fx_hat, Re Fy_hat, Im Fy_hat) of mode

@@ -48,6 +48,8 @@ rlb_status check_cfg(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
   if (!c) return afail(RLB_EINVAL, "config is null");
   if (lat->tau_k > 0.0)
     return afail(RLB_EUNSUPPORTED, "the adjoint needs a constant relaxation time (rlb_set_relaxation_time)");
+  if (lat->p.flags & RLB_OPEN_X)
+    return afail(RLB_EUNSUPPORTED, "the adjoint supports periodic x borders only");
   if (c->nsteps < 2 || (c->nsteps & 1)) return afail(RLB_EINVAL, "nsteps must be even and >= 2");
   if (c->checkpoint < 1) return afail(RLB_EINVAL, "checkpoint interval must be >= 1");
   if (c->objective != RLB_OBJ_CURRENT && c->objective != RLB_OBJ_DISSIPATION)

@@ -62,7 +62,7 @@ rlb_status check_params(const rlb_params* p) {
   if (!std::isfinite(p->cfl) || !(p->cfl > 0.0) || p->cfl > 1.0)
     return fail(p->cfl > 1.0 && std::isfinite(p->cfl) ? RLB_EUNSUPPORTED : RLB_EINVAL,
                 "cfl must be in (0, 1] (bilinear pull over a one-node neighbourhood)");
-  if (p->flags & ~(RLB_WALLS_Y | RLB_FULL26)) return fail(RLB_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~(RLB_WALLS_Y | RLB_FULL26 | RLB_OPEN_X)) return fail(RLB_EINVAL, "unknown flags 0x%x", p->flags);
   if (!std::isfinite(p->eps_ref) || !std::isfinite(p->n_ref))
     return fail(RLB_EINVAL, "eps_ref and n_ref must be finite");
   return RLB_OK;
@@ -241,6 +241,7 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   lat->d_desc = (LatDesc*)(lat->ws + w.desc_off);
   lat->num_cu = prop.multiProcessorCount;
   lat->shape = LaunchShape{4, 0, 16};
+  lat->open = OpenArgs{0.0, 0.0, p->n_ref, p->eps_ref, 0.0, 0.0, nullptr};
   lat->desc.state[0] = lat->state[0];
   lat->desc.state[1] = lat->state[1];
   lat->desc.mask = lat->mask;
@@ -432,8 +433,40 @@ rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps) {
       lat->ev_pending |= 1u << slot;
     }
     lat->cur ^= 1;
+    if (lat->p.flags & RLB_OPEN_X)
+      HIP_TRY(launch_open_borders(lat, lat->state[lat->cur]), "open borders");
     lat->step += 1;
   }
+  return RLB_OK;
+}
+
+rlb_status rlb_set_open_borders(rlb_lattice* lat, double bx, double by, double n_in, double eps_out) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!(lat->p.flags & RLB_OPEN_X)) return fail(RLB_EINVAL, "the lattice was created without RLB_OPEN_X");
+  if (!std::isfinite(bx) || !std::isfinite(by) || !(bx * bx + by * by < 1.0))
+    return fail(RLB_EINVAL, "inlet velocity must be finite with |beta| < 1");
+  if (!std::isfinite(n_in)) return fail(RLB_EINVAL, "inlet charge density must be finite");
+  if (!std::isfinite(eps_out) || !(eps_out > 0.0)) return fail(RLB_EINVAL, "outlet energy density must be > 0");
+  lat->open.bx = bx;
+  lat->open.by = by;
+  lat->open.n_in = n_in;
+  lat->open.eps_out = eps_out;
+  return RLB_OK;
+}
+
+rlb_status rlb_column_current(rlb_lattice* lat, int32_t x, double* d_out) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (x < 0 || x >= lat->p.nx) return fail(RLB_EINVAL, "column %d outside [0, %d)", x, lat->p.nx);
+  if (!d_out || !aligned(d_out, 8)) return fail(RLB_EINVAL, "d_out must be an 8-byte aligned device pointer");
+  HIP_TRY(launch_column_current(lat, x, d_out), "column current");
+  return RLB_OK;
+}
+
+rlb_status rlb_power_spectrum(const double* d_series, int64_t n, double* d_out, void* hip_stream) {
+  if (!d_series || !d_out || !aligned(d_series, 8) || !aligned(d_out, 8))
+    return fail(RLB_EINVAL, "series and output must be 8-byte aligned device pointers");
+  if (n < 2 || n > ((int64_t)1 << 26)) return fail(RLB_EINVAL, "series length must be in [2, 2^26]");
+  HIP_TRY(launch_power_spectrum(d_series, n, d_out, (hipStream_t)hip_stream), "power spectrum");
   return RLB_OK;
 }
 

@@ -89,6 +89,8 @@ struct BatchLayout {
 rlb_status batch_layout(const rlb_params* p, int count, const int32_t* nx, const int32_t* ny,
                         BatchLayout& L) {
   if (!p) return bfail(RLB_EINVAL, "params is null");
+  if (p->flags & RLB_OPEN_X)
+    return bfail(RLB_EUNSUPPORTED, "open x borders are not supported in batches");
   if (count < 1 || count > 65536) return bfail(RLB_EINVAL, "count must be in [1, 65536]");
   if (!nx || !ny) return bfail(RLB_EINVAL, "size arrays are null");
   size_t off = 0;

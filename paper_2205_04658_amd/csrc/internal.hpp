@@ -120,6 +120,15 @@ struct ObjArgs {
   int32_t nx, ny, row, kind;   // kind 2 counts fluid nodes
 };
 
+// Open x borders (boundary.hip): velocity inlet at x = 0, pressure outlet
+// at x = nx - 1.
+struct OpenArgs {
+  double bx, by, n_in;    // inlet 3-velocity and charge density
+  double eps_out;         // outlet energy density
+  double eps_ref, n_ref;  // storage references (filled at launch)
+  uint32_t* err;
+};
+
 struct Workspace {
   size_t state_off[2], mask_off, coef_off, modes_off, bins_off, table_off,
       phase_off, force_off, twiddle_off, partial_off, desc_off, misc_off, total;
@@ -160,6 +169,7 @@ struct rlb_lattice {
   // forcing
   double fx, fy;
   double tau_k;           // per-node relaxation from eta/s (0 = constant tau)
+  rlb::OpenArgs open;     // open x borders (RLB_OPEN_X)
   bool stir;
   double kmin, kmax, amp;
   uint64_t seed;
@@ -193,6 +203,9 @@ int tiles_of(int nx, int ny, int tile_rows);
 std::vector<LaunchShape> launch_candidates(int Q);
 hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode,
                        int parity, float* fields, uint32_t field_mask);
+hipError_t launch_open_borders(const rlb_lattice* lat, float* state);
+hipError_t launch_column_current(const rlb_lattice* lat, int x, double* out);
+hipError_t launch_power_spectrum(const double* s, int64_t n, double* out, hipStream_t st);
 hipError_t launch_init(const rlb_lattice* lat, const float* eps,
                        const float* bx, const float* by, const float* n,
                        float* dst);

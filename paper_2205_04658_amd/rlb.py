@@ -17,6 +17,7 @@ STATUS_NAMES = ["RLB_OK", "RLB_EINVAL", "RLB_EDEVICE", "RLB_ENOMEM", "RLB_ENONFI
                 "RLB_ELANDAU", "RLB_ESTATE", "RLB_EUNSUPPORTED"]
 WALLS_Y = 0x1
 FULL26 = 0x2
+OPEN_X = 0x4
 FIELDS = ["eps", "beta_x", "beta_y", "n", "T00", "T0x", "T0y", "Txx", "Txy", "Tyy",
           "J0", "Jx", "Jy"]
 
@@ -34,7 +35,7 @@ SYMBOLS = [
     "rlb_batch_set_launch_shape", "rlb_batch_get_launch_shape", "rlb_batch_autotune",
     "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
     "rlb_set_relaxation_time", "rlb_set_relaxation_eta_s", "rlb_adjoint_workspace_bytes",
-    "rlb_adjoint_run",
+    "rlb_adjoint_run", "rlb_set_open_borders", "rlb_column_current", "rlb_power_spectrum",
 ]
 OBJECTIVES = {"current": 0, "dissipation": 1}
 
@@ -124,6 +125,9 @@ def lib():
         "rlb_batch_timing_read": [_vp, _P(_d), _P(_i64)],
         "rlb_set_relaxation_time": [_vp, _d],
         "rlb_set_relaxation_eta_s": [_vp, _d, _d],
+        "rlb_set_open_borders": [_vp, _d, _d, _d, _d],
+        "rlb_column_current": [_vp, _i32, _vp],
+        "rlb_power_spectrum": [_vp, _i64, _vp, _vp],
         "rlb_adjoint_workspace_bytes": [_vp, _P(AdjointCfg), _P(_sz)],
         "rlb_adjoint_run": [_vp, _P(AdjointCfg), _vp, _sz, _P(_d), _vp],
     }
@@ -191,7 +195,7 @@ class Lattice:
     this object; all work goes to the torch stream current at creation."""
 
     def __init__(self, nx, ny, tau, cfl=1.0, walls=False, full26=False,
-                 eps_ref=1.0, n_ref=0.1, device=None, _member=None):
+                 eps_ref=1.0, n_ref=0.1, device=None, open_x=False, _member=None):
         torch = _torch()
         if _member is not None:          # a batch member: handle owned by the batch
             batch, h = _member
@@ -200,7 +204,7 @@ class Lattice:
             self._h, self._owned, self._batch, self._keep = h, False, batch, []
             return
         self.nx, self.ny = int(nx), int(ny)
-        flags = (WALLS_Y if walls else 0) | (FULL26 if full26 else 0)
+        flags = (WALLS_Y if walls else 0) | (FULL26 if full26 else 0) | (OPEN_X if open_x else 0)
         self.params = Params(self.nx, self.ny, float(tau), float(cfl), flags,
                              float(eps_ref), float(n_ref))
         n = _sz()
@@ -380,6 +384,24 @@ class Lattice:
     def set_relaxation_time(self, tau):
         check(lib().rlb_set_relaxation_time(self._h, float(tau)))
 
+    def set_open_borders(self, bx, by, n_in, eps_out):
+        """Velocity inlet at x = 0 (beta, n_in), pressure outlet at x = nx-1
+        (eps_out); the lattice must be created with open_x=True."""
+        check(lib().rlb_set_open_borders(self._h, float(bx), float(by), float(n_in), float(eps_out)))
+
+    def column_current(self, x, out=None):
+        """j at column x of the current step into out[0] (a float64 device
+        tensor; a new 1-element tensor if None), asynchronously."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_cuda:
+            raise ValueError("out must be a float64 device tensor")
+        self._in(out)
+        check(lib().rlb_column_current(self._h, int(x), _vp(out.data_ptr())))
+        self._out()
+        return out
+
     def set_relaxation_eta_s(self, eta_over_s, dt):
         """Per-node tau(x) = 5 (eta/s) / (T(x) dt), T = (pi^2 eps / 3)^(1/4)."""
         check(lib().rlb_set_relaxation_eta_s(self._h, float(eta_over_s), float(dt)))
@@ -409,11 +431,11 @@ class Batch:
     are Lattice objects (`batch[b]`) for initialisation and read-out."""
 
     def __init__(self, sizes, tau, cfl=1.0, walls=False, full26=False, eps_ref=1.0,
-                 n_ref=0.1, device=None):
+                 n_ref=0.1, device=None, open_x=False):
         torch = _torch()
         self.sizes = [(int(a), int(b)) for a, b in sizes]
         n = len(self.sizes)
-        flags = (WALLS_Y if walls else 0) | (FULL26 if full26 else 0)
+        flags = (WALLS_Y if walls else 0) | (FULL26 if full26 else 0) | (OPEN_X if open_x else 0)
         self.params = Params(0, 0, float(tau), float(cfl), flags, float(eps_ref), float(n_ref))
         self._nx = (_i32 * n)(*[a for a, _ in self.sizes])
         self._ny = (_i32 * n)(*[b for _, b in self.sizes])
@@ -525,6 +547,20 @@ def _autograd():
             return gout * g.to(gout.device), None, None, None, None, None, None
 
     return RLBObjective
+
+
+def power_spectrum(series):
+    """One-sided power spectrum of a float64 device series' fluctuations
+    (rlb_power_spectrum): a tensor of n // 2 + 1 bins on the series' device,
+    computed on the current stream."""
+    torch = _torch()
+    s = series.contiguous()
+    if s.dtype != torch.float64 or not s.is_cuda or s.dim() != 1:
+        raise ValueError("series must be a 1-D float64 device tensor")
+    out = torch.empty(s.numel() // 2 + 1, dtype=torch.float64, device=s.device)
+    check(lib().rlb_power_spectrum(_vp(s.data_ptr()), s.numel(), _vp(out.data_ptr()),
+                                   _stream_ptr(torch.cuda.current_stream(s.device))))
+    return out
 
 
 def rlb_objective(theta, lattice, fields, modes, nsteps, checkpoint, objective="current"):

@@ -36,6 +36,35 @@ ADJOINT = dict(nx=512, ny=256, fraction=0.05, radius=6.0, seed=7, tau=0.8,
                body_force=1e-6, steps=2000, checkpoint=100, eps=1.0, n=0.1,
                nmodes=32, kmin=7.0, kmax=9.0, mode_amplitude=1e-6)
 
+# Part II channel (Ch. 6 "Model and Methods"): a 40 x 10 um sample on a
+# 1024 x 256 lattice (spacing 0.038 um), flow entering at 0.1 v_F (lattice
+# speed 1 = v_F) through the inlet column, periodic lateral borders, one or
+# two rigid impurities of diameter 0.5 um (radius 0.25 / 0.038 nodes) in the
+# obstruction region near the inlet, the second one behind and to the side
+# of the first at a chosen separation.  tau is chosen (the paper's graphene
+# viscosity is below the scheme's interpolation viscosity at cfl = 1):
+# tau = 0.6 gives Re = U D / nu_eff = 0.1 * 13.2 / 0.075 = 17.5, near the
+# paper's 6.4 - 12.7, and the run starts from the uniform inflow state (an
+# impulsive start from rest, or tau <= 0.55, is not stable with these
+# borders).
+PART2 = dict(nx=1024, ny=256, tau=0.6, eps=1.0, n=0.1, beta_in=0.1, eps_out=1.0,
+             spacing_um=0.038, diameter_um=0.5, first=(128.0, 128.0), angle_deg=25.0,
+             separations_um=(1.68, 2.34, 3.38, 6.02, 8.39), steps=20000)
+
+
+def part2_discs(separation_um=None, angle_deg=None, cfg=PART2):
+    """[(x, y, r)] of the Part II impurities: the first at cfg['first'], the
+    second (if a separation in um is given) at that distance, rotated
+    angle_deg from the flow direction."""
+    r = 0.5 * cfg["diameter_um"] / cfg["spacing_um"]
+    x0, y0 = cfg["first"]
+    out = [(x0, y0, r)]
+    if separation_um is not None:
+        a = np.deg2rad(cfg["angle_deg"] if angle_deg is None else angle_deg)
+        d = separation_um / cfg["spacing_um"]
+        out.append((x0 + d * np.cos(a), y0 + d * np.sin(a), r))
+    return out
+
 
 def uniform(nx, ny, eps=1.0, n=0.1):
     """Fluid at rest: eps, beta_x, beta_y, n arrays (Ny, Nx) float32."""
