@@ -61,3 +61,42 @@ def power_spectrum(series):
         ph = 2.0 * np.pi * ((k * t) % n) / n
         out[k] = (np.dot(d, np.cos(ph)) ** 2 + np.dot(d, np.sin(ph)) ** 2) / float(n) ** 2
     return out
+
+
+# --------------------------------------------------------------------------
+# Part I analysis (Ch. 4, "Model and Methods" and "Results"): velocities
+# filtered to the inertial range, E(k) averaged over decorrelated samples,
+# and the power-law slope of the inertial range
+# --------------------------------------------------------------------------
+def filtered_velocity(bx, by, k_cut):
+    """The velocity with its driven range removed: beta keeps only the
+    Fourier modes with |k| < k_cut (integer wave numbers, numpy.fft
+    frequencies).  Returns (bx_f, by_f, mean |beta_f|, rms |beta_f|)."""
+    ny, nx = bx.shape
+    kx = np.fft.fftfreq(nx, 1.0 / nx)
+    ky = np.fft.fftfreq(ny, 1.0 / ny)
+    keep = (kx[None, :] ** 2 + ky[:, None] ** 2) < k_cut ** 2
+    fx = np.real(np.fft.ifft2(np.fft.fft2(bx) * keep))
+    fy = np.real(np.fft.ifft2(np.fft.fft2(by) * keep))
+    speed = np.sqrt(fx * fx + fy * fy)
+    return fx, fy, float(speed.mean()), float(np.sqrt((speed * speed).mean()))
+
+
+def spectrum_average(samples):
+    """Mean and standard error of E(k) over M samples taken a
+    decorrelation stride apart: samples (M, K) -> (mean (K,), stderr (K,)),
+    stderr = sqrt(sum_m (E_m - mean)^2 / (M (M - 1)))."""
+    s = np.asarray(samples, np.float64)
+    m = s.shape[0]
+    mean = s.mean(axis=0)
+    err = np.sqrt(((s - mean) ** 2).sum(axis=0) / (m * (m - 1))) if m > 1 else np.zeros_like(mean)
+    return mean, err
+
+
+def power_law_fit(k, E):
+    """Least-squares fit of log E = a + slope log k; returns (slope, a)."""
+    x = np.log(np.asarray(k, np.float64))
+    y = np.log(np.asarray(E, np.float64))
+    A = np.stack([x, np.ones_like(x)], axis=1)
+    (slope, a), *_ = np.linalg.lstsq(A, y, rcond=None)
+    return float(slope), float(a)
