@@ -248,6 +248,33 @@ def run_part2(torch, rlb, workloads, steps=2000, warmup=100):
     return out
 
 
+def run_analysis(torch, rlb, workloads, reps=5):
+    """The Part I analysis on forced lattices: one E(k) + filtered-speed
+    evaluation (velocity read-out, float64 2D transform, shells, inverse
+    transform of the low-pass field) at 1024^2 (shell 7-9) and 4096^2
+    (shell 31-33), k_cut = 6, averaged over `reps` calls after a warm one."""
+    out = {}
+    for n, (kmin, kmax) in ((1024, (7.0, 9.0)), (4096, (31.0, 33.0))):
+        lat = rlb.Lattice(n, n, 0.55)
+        f = workloads.uniform(n, n)
+        lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        lat.set_stirring(kmin, kmax, 1e-5, 2205)
+        lat.step(20)
+        lat.energy_spectrum(n // 2, 6.0)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record(lat.stream)
+        for _ in range(reps):
+            E, sp = lat.energy_spectrum(n // 2, 6.0)
+        e.record(lat.stream)
+        e.synchronize()
+        out[f"{n}x{n}"] = dict(ms=s.elapsed_time(e) / reps, E_peak_shell=int(E[1:].argmax()) + 1,
+                               filtered_rms=float(sp[0]))
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_adjoint(torch, rlb, workloads):
     """The gradient workload: 512 x 256 channel, walls, discs of radius 6 at
     5 % area (seed 7), tau 0.8, F = 1e-6 x_hat + 32 basis modes (7 <= |k| <=
@@ -333,6 +360,7 @@ def main():
     part2 = None
     if not a.no_part2:
         part2 = run_part2(torch, rlb, workloads)
+        part2["analysis"] = run_analysis(torch, rlb, workloads)
     adjoint = None
     if not a.no_adjoint:
         adjoint = run_adjoint(torch, rlb, workloads)

@@ -222,6 +222,34 @@ rlb_status rlb_column_current(rlb_lattice* lat, int32_t x, double* d_out);
  * line.  d_out must not overlap d_series. */
 rlb_status rlb_power_spectrum(const double* d_series, int64_t n, double* d_out, void* hip_stream);
 
+/* Spectral analysis of the current velocity field (Ch. 2 "Turbulence":
+ * E(k) = dE/dk from 1/2 |v~(k)|^2 over integer shells; Ch. 4 "Model and
+ * Methods": velocities filtered to remove the driven range).  nx and ny
+ * must be powers of two in [4, 4096] (RLB_EUNSUPPORTED otherwise).
+ * rlb_energy_spectrum reads beta (as rlb_read_fields), transforms it in
+ * float64 and writes, on the lattice stream:
+ *   d_out[s] = E(s) = 1/2 sum_{s-1/2 <= |k| < s+1/2} |beta~(k)|^2 / (nx ny)^2,
+ *              s = 0 .. kmax (numpy.fft conventions, integer wave numbers);
+ *   d_out[kmax+1] = rms |beta_f|, d_out[kmax+2] = mean |beta_f|, beta_f the
+ *              velocity keeping only the modes with |k| < k_cut;
+ * and, if d_acc is not null, adds E(s) to d_acc[s] and E(s)^2 to
+ * d_acc[kmax+1+s] (running sums for time averages).  d_work: a 256-byte
+ * aligned device buffer of rlb_spectrum_workspace_bytes.  Deterministic. */
+rlb_status rlb_spectrum_workspace_bytes(const rlb_lattice* lat, int32_t kmax, size_t* bytes);
+rlb_status rlb_energy_spectrum(rlb_lattice* lat, int32_t kmax, double k_cut, double* d_out,
+                               double* d_acc, void* d_work, size_t bytes);
+
+/* Host helpers of the analysis (no device work).  rlb_spectrum_average: mean
+ * and standard error sqrt(sum (E - mean)^2 / (M (M-1))) per shell from the
+ * running sums of M = count samples taken a decorrelation stride apart
+ * (h_acc as d_acc above, copied to the host).  rlb_power_law_fit:
+ * least-squares log y = intercept + slope log k over n > 1 points (k, y > 0),
+ * e.g. the inertial range of E(k) against the k^-5/3 law. */
+rlb_status rlb_spectrum_average(const double* h_acc, int32_t kmax, int64_t count, double* h_mean,
+                                double* h_err);
+rlb_status rlb_power_law_fit(const double* h_k, const double* h_y, int32_t n, double* h_slope,
+                             double* h_intercept);
+
 /* Stirring coefficients of a given step without advancing anything:
  * d_out[4m .. 4m+3] = (Re Fx_hat, Im Fx_hat, Re Fy_hat, Im Fy_hat) of mode
  * m, float64.  *count receives the number of half-shell modes. */

@@ -440,6 +440,68 @@ rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps) {
   return RLB_OK;
 }
 
+static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+static rlb_status check_spectrum(const rlb_lattice* lat, int32_t kmax) {
+  if (!pow2_in(lat->p.nx, 4, 4096) || !pow2_in(lat->p.ny, 4, 4096))
+    return fail(RLB_EUNSUPPORTED, "spectral analysis needs nx and ny powers of two in [4, 4096]");
+  if (kmax < 0 || kmax > 65535) return fail(RLB_EINVAL, "kmax must be in [0, 65535]");
+  return RLB_OK;
+}
+
+rlb_status rlb_spectrum_workspace_bytes(const rlb_lattice* lat, int32_t kmax, size_t* bytes) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (rlb_status s = check_spectrum(lat, kmax)) return s;
+  if (!bytes) return fail(RLB_EINVAL, "bytes is null");
+  *bytes = spectral_layout(lat->p.nx, lat->p.ny, kmax).total;
+  return RLB_OK;
+}
+
+rlb_status rlb_energy_spectrum(rlb_lattice* lat, int32_t kmax, double k_cut, double* d_out,
+                               double* d_acc, void* d_work, size_t bytes) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (rlb_status s = check_spectrum(lat, kmax)) return s;
+  if (!std::isfinite(k_cut) || k_cut < 0.0) return fail(RLB_EINVAL, "k_cut must be finite and >= 0");
+  if (!d_out || !aligned(d_out, 8) || (d_acc && !aligned(d_acc, 8)))
+    return fail(RLB_EINVAL, "d_out (and d_acc) must be 8-byte aligned device pointers");
+  if (!d_work || !aligned(d_work, 256)) return fail(RLB_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  const size_t need = spectral_layout(lat->p.nx, lat->p.ny, kmax).total;
+  if (bytes < need) return fail(RLB_ENOMEM, "spectral workspace has %zu bytes, needs %zu", bytes, need);
+  HIP_TRY(launch_spectrum(lat, kmax, k_cut, d_out, d_acc, (char*)d_work), "energy spectrum");
+  return RLB_OK;
+}
+
+rlb_status rlb_spectrum_average(const double* h_acc, int32_t kmax, int64_t count, double* h_mean,
+                                double* h_err) {
+  if (!h_acc || !h_mean || !h_err) return fail(RLB_EINVAL, "null pointer");
+  if (kmax < 0 || count < 1) return fail(RLB_EINVAL, "kmax must be >= 0 and count >= 1");
+  const double m = (double)count;
+  for (int s = 0; s <= kmax; ++s) {
+    const double mean = h_acc[s] / m;
+    const double ss = h_acc[kmax + 1 + s] - m * mean * mean;   // sum (E - mean)^2
+    h_mean[s] = mean;
+    h_err[s] = count > 1 ? std::sqrt(std::max(ss, 0.0) / (m * (m - 1.0))) : 0.0;
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_power_law_fit(const double* h_k, const double* h_y, int32_t n, double* h_slope,
+                             double* h_intercept) {
+  if (!h_k || !h_y || !h_slope || !h_intercept) return fail(RLB_EINVAL, "null pointer");
+  if (n < 2) return fail(RLB_EINVAL, "need at least two points");
+  double sx = 0, sy = 0, sxx = 0, sxy = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!(h_k[i] > 0.0) || !(h_y[i] > 0.0)) return fail(RLB_EINVAL, "k and y must be positive");
+    const double x = std::log(h_k[i]), y = std::log(h_y[i]);
+    sx += x; sy += y; sxx += x * x; sxy += x * y;
+  }
+  const double d = n * sxx - sx * sx;
+  if (!(d > 0.0)) return fail(RLB_EINVAL, "the k values must not all be equal");
+  *h_slope = (n * sxy - sx * sy) / d;
+  *h_intercept = (sy - *h_slope * sx) / n;
+  return RLB_OK;
+}
+
 rlb_status rlb_set_open_borders(rlb_lattice* lat, double bx, double by, double n_in, double eps_out) {
   if (rlb_status s = check_lat(lat)) return s;
   if (!(lat->p.flags & RLB_OPEN_X)) return fail(RLB_EINVAL, "the lattice was created without RLB_OPEN_X");

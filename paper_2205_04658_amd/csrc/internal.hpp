@@ -129,6 +129,11 @@ struct OpenArgs {
   uint32_t* err;
 };
 
+// Spectral analysis scratch (spectral.hip), carved from a caller workspace.
+struct SpectralLayout {
+  size_t z_off, fields_off, twx_off, twy_off, part_off, speed_off, total;
+};
+
 struct Workspace {
   size_t state_off[2], mask_off, coef_off, modes_off, bins_off, table_off,
       phase_off, force_off, twiddle_off, partial_off, desc_off, misc_off, total;
@@ -203,6 +208,9 @@ int tiles_of(int nx, int ny, int tile_rows);
 std::vector<LaunchShape> launch_candidates(int Q);
 hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode,
                        int parity, float* fields, uint32_t field_mask);
+SpectralLayout spectral_layout(int nx, int ny, int kmax);
+hipError_t launch_spectrum(rlb_lattice* lat, int kmax, double kcut, double* out, double* acc,
+                           char* ws);
 hipError_t launch_open_borders(const rlb_lattice* lat, float* state);
 hipError_t launch_column_current(const rlb_lattice* lat, int x, double* out);
 hipError_t launch_power_spectrum(const double* s, int64_t n, double* out, hipStream_t st);

@@ -36,6 +36,8 @@ SYMBOLS = [
     "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
     "rlb_set_relaxation_time", "rlb_set_relaxation_eta_s", "rlb_adjoint_workspace_bytes",
     "rlb_adjoint_run", "rlb_set_open_borders", "rlb_column_current", "rlb_power_spectrum",
+    "rlb_spectrum_workspace_bytes", "rlb_energy_spectrum", "rlb_spectrum_average",
+    "rlb_power_law_fit",
 ]
 OBJECTIVES = {"current": 0, "dissipation": 1}
 
@@ -128,6 +130,10 @@ def lib():
         "rlb_set_open_borders": [_vp, _d, _d, _d, _d],
         "rlb_column_current": [_vp, _i32, _vp],
         "rlb_power_spectrum": [_vp, _i64, _vp, _vp],
+        "rlb_spectrum_workspace_bytes": [_vp, _i32, _P(_sz)],
+        "rlb_energy_spectrum": [_vp, _i32, _d, _vp, _vp, _vp, _sz],
+        "rlb_spectrum_average": [_vp, _i32, _i64, _vp, _vp],
+        "rlb_power_law_fit": [_vp, _vp, _i32, _P(_d), _P(_d)],
         "rlb_adjoint_workspace_bytes": [_vp, _P(AdjointCfg), _P(_sz)],
         "rlb_adjoint_run": [_vp, _P(AdjointCfg), _vp, _sz, _P(_d), _vp],
     }
@@ -402,6 +408,26 @@ class Lattice:
         self._out()
         return out
 
+    def energy_spectrum(self, kmax=None, k_cut=0.0, acc=None):
+        """E(k) of the current velocity (rlb_energy_spectrum): returns
+        (E tensor [kmax+1], rms and mean speed of the field filtered to
+        |k| < k_cut as a 2-element tensor), all float64 on the device;
+        acc (a float64 tensor [2 (kmax+1)]) collects running sums."""
+        torch = _torch()
+        kmax = min(self.nx, self.ny) // 2 if kmax is None else int(kmax)
+        n = _sz()
+        check(lib().rlb_spectrum_workspace_bytes(self._h, kmax, ctypes.byref(n)))
+        work = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        out = torch.empty(kmax + 3, dtype=torch.float64, device=self.device)
+        if acc is not None and (acc.dtype != torch.float64 or acc.numel() != 2 * (kmax + 1)):
+            raise ValueError("acc must be a float64 tensor of 2 (kmax + 1) elements")
+        self._in(out, work, *([acc] if acc is not None else []))
+        check(lib().rlb_energy_spectrum(self._h, kmax, float(k_cut), _vp(out.data_ptr()),
+                                        _vp(acc.data_ptr()) if acc is not None else None,
+                                        _vp(work.data_ptr()), n.value))
+        self._out()
+        return out[:kmax + 1], out[kmax + 1:]
+
     def set_relaxation_eta_s(self, eta_over_s, dt):
         """Per-node tau(x) = 5 (eta/s) / (T(x) dt), T = (pi^2 eps / 3)^(1/4)."""
         check(lib().rlb_set_relaxation_eta_s(self._h, float(eta_over_s), float(dt)))
@@ -561,6 +587,27 @@ def power_spectrum(series):
     check(lib().rlb_power_spectrum(_vp(s.data_ptr()), s.numel(), _vp(out.data_ptr()),
                                    _stream_ptr(torch.cuda.current_stream(s.device))))
     return out
+
+
+def spectrum_average(acc, count):
+    """(mean, standard error) per shell from energy_spectrum's running sums
+    of `count` samples (rlb_spectrum_average, host)."""
+    a = np.ascontiguousarray(np.asarray(acc.cpu() if hasattr(acc, "cpu") else acc, np.float64))
+    kmax = a.size // 2 - 1
+    mean, err = np.empty(kmax + 1), np.empty(kmax + 1)
+    check(lib().rlb_spectrum_average(a.ctypes.data_as(_vp), kmax, int(count),
+                                     mean.ctypes.data_as(_vp), err.ctypes.data_as(_vp)))
+    return mean, err
+
+
+def power_law_fit(k, y):
+    """(slope, intercept) of log y = intercept + slope log k (rlb_power_law_fit, host)."""
+    k = np.ascontiguousarray(np.asarray(k, np.float64))
+    y = np.ascontiguousarray(np.asarray(y, np.float64))
+    slope, icpt = _d(), _d()
+    check(lib().rlb_power_law_fit(k.ctypes.data_as(_vp), y.ctypes.data_as(_vp), k.size,
+                                  ctypes.byref(slope), ctypes.byref(icpt)))
+    return slope.value, icpt.value
 
 
 def rlb_objective(theta, lattice, fields, modes, nsteps, checkpoint, objective="current"):
