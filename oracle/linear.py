@@ -26,16 +26,19 @@ from .velocity_set import velocity_set
 
 
 def stream_symbol(k, cfl=1.0):
-    """s_i(k) = sum over the 4 bilinear taps of weight * exp(-i k.offset)."""
+    """s_i(k) = sum over the 4 bilinear taps of weight * exp(-i k.offset):
+    along each axis the displacement |d| = m + a has taps m and m + 1 cells
+    upstream with weights 1 - a and a."""
     v, _, _ = velocity_set()
     s = np.zeros(v.shape[0], np.complex128)
     for i in range(v.shape[0]):
-        dx, dy = cfl * v[i, 0], cfl * v[i, 1]
-        sx, sy = np.sign(dx), np.sign(dy)
-        ax, ay = abs(dx), abs(dy)
-        ex = np.exp(-1j * k[0] * sx)
-        ey = np.exp(-1j * k[1] * sy)
-        s[i] = ((1 - ax) + ax * ex) * ((1 - ay) + ay * ey)
+        f = 1.0 + 0j
+        for ax_, kk in ((0, k[0]), (1, k[1])):
+            d = cfl * v[i, ax_]
+            sg, m = np.sign(d), np.floor(abs(d))
+            a = abs(d) - m
+            f *= np.exp(-1j * kk * sg * m) * ((1 - a) + a * np.exp(-1j * kk * sg))
+        s[i] = f
     return s
 
 

@@ -40,20 +40,27 @@ def stream(F, cfl=1.0):
 
     Population i moves by delta_i = cfl * (v_ix, v_iy) per step.  The momentum
     set is off-lattice, so the value arriving at node x is the bilinear
-    interpolation of the pre-stream field at the departure point x - delta_i.
-    The lattice has one z node, so the z displacement is the identity.
+    interpolation of the pre-stream field at the departure point x - delta_i,
+    between the two lattice nodes that bracket it along each axis: with
+    |delta| = m + a (m whole cells, 0 <= a < 1), the taps sit m and m + 1
+    cells upstream with weights 1 - a and a (for cfl <= 1, m = 0 except a
+    displacement of exactly one cell; cfl up to 2 reaches two cells, the
+    paper's time steps giving cfl = dt / dx up to 1.25, Ch. 4 "Model and
+    Methods").  The lattice has one z node, so the z displacement is the
+    identity.
     Borders are periodic in x and y (walls are solid nodes, and open x
     borders overwrite their columns after the update, see `step`).
     """
-    if not (0.0 < cfl <= 1.0):
-        raise ValueError("bilinear pull needs 0 < cfl <= 1")
+    if not (0.0 < cfl <= 2.0):
+        raise ValueError("the bilinear pull supports 0 < cfl <= 2")
     out = np.empty_like(F)
     for i in range(F.shape[0]):
         dx, dy = cfl * V[i, 0], cfl * V[i, 1]
         sx, sy = int(np.sign(dx)), int(np.sign(dy))
-        ax, ay = abs(dx), abs(dy)
-        f = F[i]
-        f_x = np.roll(f, sx, axis=1)        # f(x - sx, y)
+        mx, my = int(np.floor(abs(dx))), int(np.floor(abs(dy)))
+        ax, ay = abs(dx) - mx, abs(dy) - my
+        f = np.roll(F[i], (my * sy, mx * sx), axis=(0, 1))   # F(x - m s): the nearer taps
+        f_x = np.roll(f, sx, axis=1)        # one cell further along x
         f_y = np.roll(f, sy, axis=0)        # f(x, y - sy)
         f_xy = np.roll(f_x, sy, axis=0)     # f(x - sx, y - sy)
         out[i] = ((1 - ax) * (1 - ay) * f + ax * (1 - ay) * f_x
