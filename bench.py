@@ -110,10 +110,11 @@ print(json.dumps(dict(steps=steps, seconds=el, cells=n * n)))
                       f"{d['steps']} steps in {d['seconds']:.1f} s, float64 NumPy, 1 thread"}
 
 
-def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=None):
+def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=None, cfl=1.0):
     c = workloads.FORCED_4096
     nx, ny = c["nx"], c["ny"]
-    lat = rlb.Lattice(nx, ny, c["tau"], full26=(layout == "full26"), eps_ref=c["eps"], n_ref=c["n"])
+    lat = rlb.Lattice(nx, ny, c["tau"], cfl=cfl, full26=(layout == "full26"), eps_ref=c["eps"],
+                      n_ref=c["n"])
     f = workloads.uniform(nx, ny, c["eps"], c["n"])
     lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
     lat.set_stirring(c["kmin"], c["kmax"], c["amplitude"], c["seed"])
@@ -353,6 +354,11 @@ def main():
         variants["eta_s"] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms", "bytes_per_cell",
                                                "achieved_gbs")}
         variants["eta_s"]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
+        # the paper's largest time step: cfl = dt / dx = 1.25 (two-cell stencil)
+        v = run_plain(torch, rlb, workloads, a.layout, max(a.steps // 3, 10), a.warmup, cfl=1.25)
+        variants["cfl_1_25"] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms",
+                                                  "bytes_per_cell", "achieved_gbs")}
+        variants["cfl_1_25"]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
     batched = None
     if not a.no_batch:
         batched = run_batch(torch, rlb, workloads, max(a.steps // 5, 50), 20)

@@ -65,7 +65,13 @@ typedef enum {
  *   tau      relaxation time in time steps, tau > 1/2 (Ch. 3: eta =
  *            tau_R (eps + P) / 5; the scheme's shear viscosity is
  *            (tau - 1/2)/5 + nu_interp).
- *   cfl      dt/dx in (0, 1]; populations move cfl * (v_x, v_y) per step.
+ *   cfl      dt/dx in (0, 2]; populations move cfl * (v_x, v_y) per step,
+ *            interpolated bilinearly between the two nodes that bracket the
+ *            departure point along each axis (Ch. 3, linear interpolation;
+ *            the paper's time steps give cfl up to 1.25, Ch. 4).  cfl > 1
+ *            reaches two nodes and needs a periodic lattice (RLB_WALLS_Y and
+ *            RLB_OPEN_X give RLB_EUNSUPPORTED); rlb_adjoint_run and
+ *            rlb_column_current support cfl <= 1.
  *   flags    RLB_WALLS_Y | RLB_FULL26 | RLB_OPEN_X.
  *   eps_ref, n_ref  shifted-storage references: populations are stored as
  *            F_i - w_i eps_ref and G_i - w_i n_ref in float32 (the float32

@@ -50,6 +50,7 @@ rlb_status check_cfg(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
     return afail(RLB_EUNSUPPORTED, "the adjoint needs a constant relaxation time (rlb_set_relaxation_time)");
   if (lat->p.flags & RLB_OPEN_X)
     return afail(RLB_EUNSUPPORTED, "the adjoint supports periodic x borders only");
+  if (lat->p.cfl > 1.0) return afail(RLB_EUNSUPPORTED, "the adjoint supports cfl <= 1 only");
   if (c->nsteps < 2 || (c->nsteps & 1)) return afail(RLB_EINVAL, "nsteps must be even and >= 2");
   if (c->checkpoint < 1) return afail(RLB_EINVAL, "checkpoint interval must be >= 1");
   if (c->objective != RLB_OBJ_CURRENT && c->objective != RLB_OBJ_DISSIPATION)
@@ -256,7 +257,7 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
       AHIP(hipMemcpyAsync(store(0), ck(seg), state_copy, hipMemcpyDeviceToDevice, st), "restore");
       for (int64_t j = 0; j + 1 < len; ++j) {
         ta.lats = d_desc + j;
-        AHIP(launch_tiles(lat->Q, unit, mask, MODE_STEP, FORCE_STIR, ta, lat->shape, lat->num_cu, st),
+        AHIP(launch_tiles(lat->Q, stream_mode(lat->p.cfl), mask, MODE_STEP, FORCE_STIR, ta, lat->shape, lat->num_cu, st),
              "recompute");
       }
       for (int64_t t = t0 + len - 1; t >= t0; --t) {

@@ -59,9 +59,11 @@ rlb_status check_params(const rlb_params* p) {
   if ((int64_t)p->ny * (((int64_t)p->nx + 63) / 64 * 64) >= (int64_t)1 << 30)
     return fail(RLB_EINVAL, "ny * (nx rounded up to 64) must be < 2^30");
   if (!std::isfinite(p->tau) || !(p->tau > 0.5)) return fail(RLB_EINVAL, "tau must be finite and > 1/2");
-  if (!std::isfinite(p->cfl) || !(p->cfl > 0.0) || p->cfl > 1.0)
-    return fail(p->cfl > 1.0 && std::isfinite(p->cfl) ? RLB_EUNSUPPORTED : RLB_EINVAL,
-                "cfl must be in (0, 1] (bilinear pull over a one-node neighbourhood)");
+  if (!std::isfinite(p->cfl) || !(p->cfl > 0.0) || p->cfl > 2.0)
+    return fail(p->cfl > 2.0 && std::isfinite(p->cfl) ? RLB_EUNSUPPORTED : RLB_EINVAL,
+                "cfl must be in (0, 2] (bilinear pull over at most a two-node neighbourhood)");
+  if (p->cfl > 1.0 && (p->flags & (RLB_WALLS_Y | RLB_OPEN_X)))
+    return fail(RLB_EUNSUPPORTED, "cfl > 1 is supported on periodic lattices (no walls, no open borders)");
   if (p->flags & ~(RLB_WALLS_Y | RLB_FULL26 | RLB_OPEN_X)) return fail(RLB_EINVAL, "unknown flags 0x%x", p->flags);
   if (!std::isfinite(p->eps_ref) || !std::isfinite(p->n_ref))
     return fail(RLB_EINVAL, "eps_ref and n_ref must be finite");
@@ -97,9 +99,16 @@ int planes_of(const rlb_params* p) { return (p->flags & RLB_FULL26) ? 26 : 17; }
 template <class DS>
 void fill_taps(rlb_lattice* lat) {
   const double q = 16777216.0;   // 2^24
+  const bool wide = lat->p.cfl > 1.0;
   for (int k = 0; k < DS::Q; ++k) {
-    const double ax = lat->p.cfl * std::fabs(DS::vx[k]);
-    const double ay = lat->p.cfl * std::fabs(DS::vy[k]);
+    double ax = lat->p.cfl * std::fabs(DS::vx[k]);
+    double ay = lat->p.cfl * std::fabs(DS::vy[k]);
+    // 1 < cfl <= 2: a displacement of one cell or more starts one cell
+    // upstream (taps one and two cells away, fraction in [0, 1])
+    lat->shift[k][0] = (uint8_t)(wide && ax >= 1.0);
+    lat->shift[k][1] = (uint8_t)(wide && ay >= 1.0);
+    if (lat->shift[k][0]) ax -= 1.0;
+    if (lat->shift[k][1]) ay -= 1.0;
     const double w00 = std::nearbyint((1 - ax) * (1 - ay) * q) / q;
     const double w10 = std::nearbyint(ax * (1 - ay) * q) / q;
     const double w01 = std::nearbyint((1 - ax) * ay * q) / q;
@@ -519,6 +528,7 @@ rlb_status rlb_set_open_borders(rlb_lattice* lat, double bx, double by, double n
 rlb_status rlb_column_current(rlb_lattice* lat, int32_t x, double* d_out) {
   if (rlb_status s = check_lat(lat)) return s;
   if (x < 0 || x >= lat->p.nx) return fail(RLB_EINVAL, "column %d outside [0, %d)", x, lat->p.nx);
+  if (lat->p.cfl > 1.0) return fail(RLB_EUNSUPPORTED, "the column current supports cfl <= 1");
   if (!d_out || !aligned(d_out, 8)) return fail(RLB_EINVAL, "d_out must be an 8-byte aligned device pointer");
   HIP_TRY(launch_column_current(lat, x, d_out), "column current");
   return RLB_OK;

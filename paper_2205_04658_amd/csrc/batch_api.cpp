@@ -171,7 +171,7 @@ TileArgs tile_args(const rlb_batch* B, int parity) {
 }
 
 hipError_t launch_batch_step(const rlb_batch* B, int parity, bool mask, int force) {
-  return launch_tiles(B->Q, B->p.cfl == 1.0, mask, MODE_STEP, force, tile_args(B, parity),
+  return launch_tiles(B->Q, stream_mode(B->p.cfl), mask, MODE_STEP, force, tile_args(B, parity),
                       B->shape, B->num_cu, B->stream);
 }
 

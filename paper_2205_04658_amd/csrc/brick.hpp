@@ -113,4 +113,59 @@ __device__ __forceinline__ float pull(const float* __restrict__ base, const Nbr&
   }
 }
 
+// Two-cell neighbourhood for 1 < cfl <= 2: rows y-2 .. y+2 and columns
+// x-2 .. x+2 (periodic), index 2 is the node itself.
+struct Nbr5 {
+  int64_t r[5];
+  uint32_t c[5];
+};
+
+template <int Q>
+__device__ __forceinline__ Nbr5 neighbourhood5(int x, int y, int nx, int ny, int row) {
+  const int64_t rb = (int64_t)4 * (2 * Q) * row;
+  Nbr5 n;
+#pragma unroll
+  for (int d = -2; d <= 2; ++d) {
+    int xx = x + d, yy = y + d;
+    xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+    yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+    n.r[d + 2] = yy * rb;
+    n.c[d + 2] = col_bytes<Q>(xx);
+  }
+  return n;
+}
+
+// Pull for 1 < cfl <= 2: along each axis the displacement is m whole cells
+// (m = 0 or 1, uniform per plane: shift[0] for x, shift[1] for y) plus a
+// fraction, so the taps sit m and m + 1 cells upstream; tap[] holds the
+// bilinear weights of (near x, near y), (far x, near y), (near x, far y),
+// (far x, far y).
+template <class DS, int P, int PL>
+__device__ __forceinline__ float pull_wide(const float* __restrict__ base, const Nbr5& n,
+                                           const float* tap, const uint8_t* shift) {
+  using T = Taps<DS, P>;
+  constexpr int sx = T::sx, sy = T::sy;
+  if constexpr (sx == 0 && sy == 0) {
+    return ldp<PL>(base, n.r[2], n.c[2]);
+  } else {
+    const bool mx = shift[0] != 0, my = shift[1] != 0;
+    const uint32_t cn = sx == 0 ? n.c[2] : (mx ? n.c[2 - sx] : n.c[2]);
+    const uint32_t cf = sx == 0 ? n.c[2] : (mx ? n.c[2 - 2 * sx] : n.c[2 - sx]);
+    const int64_t rn = sy == 0 ? n.r[2] : (my ? n.r[2 - sy] : n.r[2]);
+    const int64_t rf = sy == 0 ? n.r[2] : (my ? n.r[2 - 2 * sy] : n.r[2 - sy]);
+    if constexpr (sy == 0) {
+      return tap[0] * ldp<PL>(base, rn, cn) + tap[1] * ldp<PL>(base, rn, cf);
+    } else if constexpr (sx == 0) {
+      return tap[0] * ldp<PL>(base, rn, cn) + tap[2] * ldp<PL>(base, rf, cn);
+    } else {
+      return tap[0] * ldp<PL>(base, rn, cn) + tap[1] * ldp<PL>(base, rn, cf) +
+             tap[2] * ldp<PL>(base, rf, cn) + tap[3] * ldp<PL>(base, rf, cf);
+    }
+  }
+}
+
+// Streaming modes of the step kernels: general cfl < 1, cfl = 1 (unit
+// components are plain shifts), 1 < cfl <= 2 (two-cell stencil).
+enum StreamMode : int { SM_GENERAL = 0, SM_UNIT = 1, SM_WIDE = 2 };
+
 }  // namespace rlb

@@ -34,6 +34,7 @@ enum ForceMode : int { FORCE_NONE = 0, FORCE_BODY = 1, FORCE_STIR = 2 };
 // Parameters shared by every lattice of one step launch.
 struct StepShared {
   float tap[kMaxQ][4];    // bilinear weights (w00, w10, w01, w11) per plane
+  uint8_t shift[kMaxQ][2];  // whole-cell tap shifts (x, y) per plane (cfl > 1)
   float inv_tau;           // constant 1/tau (tau_k == 0)
   double tau_k;            // > 0: per-node 1/tau = tau_k * eps^(1/4) (eta/s relaxation)
   double eps_ref, n_ref;
@@ -181,6 +182,7 @@ struct rlb_lattice {
   int nmodes, K;
   // bilinear tap weights per plane
   float tap[rlb::kMaxQ][4];
+  uint8_t shift[rlb::kMaxQ][2];   // whole-cell tap shifts (cfl > 1)
   int64_t step;
   // timing of the main step kernel
   bool timing;
@@ -199,7 +201,10 @@ void set_error_message(const char* msg);
 
 // step.hip
 StepShared shared_of(const rlb_lattice* lat);
-hipError_t launch_tiles(int Q, bool unit, bool mask, int mode, int force_mode,
+// sm: streaming mode (SM_GENERAL / SM_UNIT / SM_WIDE, see brick.hpp), from
+// stream_mode(cfl).
+int stream_mode(double cfl);
+hipError_t launch_tiles(int Q, int sm, bool mask, int mode, int force_mode,
                         const TileArgs& a, LaunchShape shape, int num_cu,
                         hipStream_t s);
 int tiles_of(int nx, int ny, int tile_rows);

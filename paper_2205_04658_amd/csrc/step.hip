@@ -23,7 +23,7 @@
 
 namespace rlb {
 
-template <class DS, bool UNIT, bool MASK, int FORCE, int MODE>
+template <class DS, int SM, bool MASK, int FORCE, int MODE>
 __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc& L,
                                             const float* __restrict__ src,
                                             float* __restrict__ dst,
@@ -31,7 +31,12 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
   constexpr int Q = DS::Q;
   const int nx = L.nx, ny = L.ny;
   const int row = L.row;   // nx rounded up to 64
-  const Nbr nb = neighbourhood<Q>(x, y, nx, ny, row);
+  Nbr nb;
+  Nbr5 nb5;
+  if constexpr (SM == SM_WIDE) nb5 = neighbourhood5<Q>(x, y, nx, ny, row);
+  else nb = neighbourhood<Q>(x, y, nx, ny, row);
+  const int64_t rs = SM == SM_WIDE ? nb5.r[2] : nb.r[1];   // the node's own row and column
+  const uint32_t cs = SM == SM_WIDE ? nb5.c[2] : nb.c[1];
   const uint32_t node = (uint32_t)(y * nx + x);   // dense index (mask, fields)
   const StepShared& a = sh;
 
@@ -39,8 +44,13 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
   float f[Q], g[Q];
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
-    f[p] = pull<DS, UNIT, p, p, false>(src, nb, a.tap[p]);
-    g[p] = pull<DS, UNIT, p, Q + p, false>(src, nb, a.tap[p]);
+    if constexpr (SM == SM_WIDE) {
+      f[p] = pull_wide<DS, p, p>(src, nb5, a.tap[p], a.shift[p]);
+      g[p] = pull_wide<DS, p, Q + p>(src, nb5, a.tap[p], a.shift[p]);
+    } else {
+      f[p] = pull<DS, SM == SM_UNIT, p, p, false>(src, nb, a.tap[p]);
+      g[p] = pull<DS, SM == SM_UNIT, p, Q + p, false>(src, nb, a.tap[p]);
+    }
   });
 
   float Fsx = 0.0f, Fsy = 0.0f;   // stirring force, loaded with the populations
@@ -123,8 +133,8 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
       atomicOr(a.err, ERR_LANDAU);
       static_for<0, Q>([&](auto P) {
         constexpr int p = decltype(P)::value;
-        stp<p>(dst, nb.r[1], nb.c[1], f[p]);
-        stp<Q + p>(dst, nb.r[1], nb.c[1], g[p]);
+        stp<p>(dst, rs, cs, f[p]);
+        stp<Q + p>(dst, rs, cs, g[p]);
       });
       return;
     }
@@ -190,8 +200,8 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
       if constexpr (q == p) {
         const float fn = f[p] - w0 * (f[p] - w * ec.A) - w * p0;
         const float gn = g[p] - w0 * (g[p] - w * ec.Ag);
-        stp<p>(dst, nb.r[1], nb.c[1], solid ? f[p] : fn);
-        stp<Q + p>(dst, nb.r[1], nb.c[1], solid ? g[p] : gn);
+        stp<p>(dst, rs, cs, solid ? f[p] : fn);
+        stp<Q + p>(dst, rs, cs, solid ? g[p] : gn);
       } else if constexpr (q > p) {
         constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
         constexpr float vxx = (float)(DS::vx[p] * DS::vx[p]);
@@ -212,16 +222,16 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
         }
         const float ga = g[p] - oa * (g[p] - (g0 + g1));
         const float gb = g[q] - ob * (g[q] - (g0 - g1));
-        stp<p>(dst, nb.r[1], nb.c[1], solid ? f[q] : fa);
-        stp<q>(dst, nb.r[1], nb.c[1], solid ? f[p] : fb);
-        stp<Q + p>(dst, nb.r[1], nb.c[1], solid ? g[q] : ga);
-        stp<Q + q>(dst, nb.r[1], nb.c[1], solid ? g[p] : gb);
+        stp<p>(dst, rs, cs, solid ? f[q] : fa);
+        stp<q>(dst, rs, cs, solid ? f[p] : fb);
+        stp<Q + p>(dst, rs, cs, solid ? g[q] : ga);
+        stp<Q + q>(dst, rs, cs, solid ? g[p] : gb);
       }
     });
   }
 }
 
-template <class DS, bool UNIT, bool MASK, int FORCE, int MODE, int TY>
+template <class DS, int SM, bool MASK, int FORCE, int MODE, int TY>
 __global__ __launch_bounds__(64 * TY) void tile_kernel(const TileArgs a) {
   const int xcd = blockIdx.x & 7;
   const int per = gridDim.x >> 3;
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(64 * TY) void tile_kernel(const TileArgs a) {
     const int x = (st * sw + (in - ty * w)) * 64 + lane;
     const int y = __builtin_amdgcn_readfirstlane(ty * TY + row);
     if (x < L.nx && y < L.ny)
-      node_update<DS, UNIT, MASK, FORCE, MODE>(a.sh, L, L.state[a.parity],
+      node_update<DS, SM, MASK, FORCE, MODE>(a.sh, L, L.state[a.parity],
                                                const_cast<float*>(L.state[a.parity ^ 1]),
                                                a.fields, x, y);
   }
@@ -330,8 +340,11 @@ __global__ __launch_bounds__(256) void fill_u8_kernel(uint8_t* p, size_t n,
 // ---------------------------------------------------------------------------
 StepShared shared_of(const rlb_lattice* lat) {
   StepShared a;
-  for (int p = 0; p < kMaxQ; ++p)
+  for (int p = 0; p < kMaxQ; ++p) {
     for (int c = 0; c < 4; ++c) a.tap[p][c] = lat->tap[p][c];
+    a.shift[p][0] = lat->shift[p][0];
+    a.shift[p][1] = lat->shift[p][1];
+  }
   a.inv_tau = (float)(1.0 / lat->p.tau);
   a.tau_k = lat->tau_k;
   a.eps_ref = lat->p.eps_ref;
@@ -356,48 +369,53 @@ std::vector<LaunchShape> launch_candidates(int Q) {
   return c;
 }
 
-template <class DS, bool UNIT, bool MASK, int FORCE, int MODE, int TY>
+template <class DS, int SM, bool MASK, int FORCE, int MODE, int TY>
 static void go(const TileArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((tile_kernel<DS, UNIT, MASK, FORCE, MODE, TY>), dim3(grid),
+  hipLaunchKernelGGL((tile_kernel<DS, SM, MASK, FORCE, MODE, TY>), dim3(grid),
                      dim3(64 * TY), 0, s, a);
 }
 
 // Tile heights other than 4 are compiled for the folded set's step kernels
 // only (the autotuner's search space); everything else uses 4.
-template <class DS, bool UNIT, bool MASK, int FORCE, int MODE>
+template <class DS, int SM, bool MASK, int FORCE, int MODE>
 static void by_rows(int ty, const TileArgs& a, int grid, hipStream_t s) {
   if constexpr (DS::Q == 17 && MODE == MODE_STEP) {
     switch (ty) {
-      case 1: go<DS, UNIT, MASK, FORCE, MODE, 1>(a, grid, s); return;
-      case 2: go<DS, UNIT, MASK, FORCE, MODE, 2>(a, grid, s); return;
-      case 8: go<DS, UNIT, MASK, FORCE, MODE, 8>(a, grid, s); return;
+      case 1: go<DS, SM, MASK, FORCE, MODE, 1>(a, grid, s); return;
+      case 2: go<DS, SM, MASK, FORCE, MODE, 2>(a, grid, s); return;
+      case 8: go<DS, SM, MASK, FORCE, MODE, 8>(a, grid, s); return;
       default: break;
     }
   }
-  go<DS, UNIT, MASK, FORCE, MODE, 4>(a, grid, s);
+  go<DS, SM, MASK, FORCE, MODE, 4>(a, grid, s);
 }
 
-template <class DS, bool UNIT, bool MASK>
+template <class DS, int SM, bool MASK>
 static void by_force(int mode, int force, int ty, const TileArgs& a, int grid, hipStream_t s) {
-  if (mode == MODE_FIELDS) return by_rows<DS, UNIT, MASK, FORCE_NONE, MODE_FIELDS>(4, a, grid, s);
-  if (force == FORCE_NONE) return by_rows<DS, UNIT, MASK, FORCE_NONE, MODE_STEP>(ty, a, grid, s);
-  if (force == FORCE_BODY) return by_rows<DS, UNIT, MASK, FORCE_BODY, MODE_STEP>(ty, a, grid, s);
-  by_rows<DS, UNIT, MASK, FORCE_STIR, MODE_STEP>(ty, a, grid, s);
+  if (mode == MODE_FIELDS) return by_rows<DS, SM, MASK, FORCE_NONE, MODE_FIELDS>(4, a, grid, s);
+  if (force == FORCE_NONE) return by_rows<DS, SM, MASK, FORCE_NONE, MODE_STEP>(ty, a, grid, s);
+  if (force == FORCE_BODY) return by_rows<DS, SM, MASK, FORCE_BODY, MODE_STEP>(ty, a, grid, s);
+  by_rows<DS, SM, MASK, FORCE_STIR, MODE_STEP>(ty, a, grid, s);
 }
 
 template <class DS>
-static void by_flags(bool unit, bool mask, int mode, int force, int ty, const TileArgs& a,
+static void by_flags(int sm, bool mask, int mode, int force, int ty, const TileArgs& a,
                      int grid, hipStream_t s) {
-  if (unit) {
-    if (mask) by_force<DS, true, true>(mode, force, ty, a, grid, s);
-    else by_force<DS, true, false>(mode, force, ty, a, grid, s);
+  if (sm == SM_UNIT) {
+    if (mask) by_force<DS, SM_UNIT, true>(mode, force, ty, a, grid, s);
+    else by_force<DS, SM_UNIT, false>(mode, force, ty, a, grid, s);
+  } else if (sm == SM_WIDE) {
+    if (mask) by_force<DS, SM_WIDE, true>(mode, force, ty, a, grid, s);
+    else by_force<DS, SM_WIDE, false>(mode, force, ty, a, grid, s);
   } else {
-    if (mask) by_force<DS, false, true>(mode, force, ty, a, grid, s);
-    else by_force<DS, false, false>(mode, force, ty, a, grid, s);
+    if (mask) by_force<DS, SM_GENERAL, true>(mode, force, ty, a, grid, s);
+    else by_force<DS, SM_GENERAL, false>(mode, force, ty, a, grid, s);
   }
 }
 
-hipError_t launch_tiles(int Q, bool unit, bool mask, int mode, int force_mode,
+int stream_mode(double cfl) { return cfl == 1.0 ? SM_UNIT : (cfl > 1.0 ? SM_WIDE : SM_GENERAL); }
+
+hipError_t launch_tiles(int Q, int sm, bool mask, int mode, int force_mode,
                         const TileArgs& a0, LaunchShape shape, int num_cu, hipStream_t s) {
   if (a0.ntiles <= 0) return hipSuccess;
   TileArgs a = a0;
@@ -413,8 +431,8 @@ hipError_t launch_tiles(int Q, bool unit, bool mask, int mode, int force_mode,
     grid = std::max(8, (num_cu * shape.grid_per_cu * 4 / ty) / 8 * 8);
     grid = std::min(grid, 8 * a.tiles_per_xcd);
   }
-  if (Q == 17) by_flags<Dir17>(unit, mask, mode, force_mode, ty, a, grid, s);
-  else by_flags<Dir26>(unit, mask, mode, force_mode, ty, a, grid, s);
+  if (Q == 17) by_flags<Dir17>(sm, mask, mode, force_mode, ty, a, grid, s);
+  else by_flags<Dir26>(sm, mask, mode, force_mode, ty, a, grid, s);
   return hipGetLastError();
 }
 
@@ -432,7 +450,7 @@ hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode, int par
   a.fields = fields;
   LaunchShape sh = lat->shape;
   if (mode != MODE_STEP) sh.grid_per_cu = 0;
-  return launch_tiles(lat->Q, lat->p.cfl == 1.0, lat->any_solid, mode, force_mode, a, sh,
+  return launch_tiles(lat->Q, stream_mode(lat->p.cfl), lat->any_solid, mode, force_mode, a, sh,
                       lat->num_cu, lat->stream);
 }
 

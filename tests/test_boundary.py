@@ -48,13 +48,20 @@ def P(**kw):
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=3), B.EINVAL), (dict(ny=0), B.EINVAL), (dict(nx=70000, ny=70000), B.EINVAL),
     (dict(tau=0.5), B.EINVAL), (dict(tau=float("nan")), B.EINVAL),
-    (dict(cfl=0.0), B.EINVAL), (dict(cfl=1.25), B.EUNSUPPORTED),
+    (dict(cfl=0.0), B.EINVAL), (dict(cfl=2.5), B.EUNSUPPORTED),
+    (dict(cfl=1.25, flags=0x1), B.EUNSUPPORTED), (dict(cfl=1.25, flags=0x4), B.EUNSUPPORTED),
     (dict(flags=0x10), B.EINVAL), (dict(eps_ref=float("inf")), B.EINVAL)])
 def test_bad_params(L, kw, status):
     n = ctypes.c_size_t(123)
     assert L.rlb_workspace_bytes(ctypes.byref(P(**kw)), ctypes.byref(n)) == status
     assert n.value == 123            # nothing written on failure
     assert len(L.rlb_last_error()) > 0
+
+
+def test_wide_cfl_is_accepted_on_periodic_lattices(L):
+    n = ctypes.c_size_t()
+    for cfl in (1.25, 2.0):
+        assert L.rlb_workspace_bytes(ctypes.byref(P(cfl=cfl)), ctypes.byref(n)) == B.OK
 
 
 def test_workspace_size(L):

@@ -76,6 +76,10 @@ CASES = {
     "stirring": dict(stir=(2.0, 4.5, 2e-4, 11)),
     "walls_discs": dict(walls=True, discs=[(20.5, 17.0, 6.0), (60.2, 25.7, 4.0)], body=(1e-4, 0.0)),
     "cfl_half_walls": dict(cfl=0.5, walls=True, discs=[(5.0, 5.0, 3.0)], stir=(1.0, 3.0, 1e-4, 5)),
+    # two-cell stencil (the paper's cfl = dt/dx up to 1.25)
+    "cfl_1_25": dict(cfl=1.25),
+    "cfl_1_6_stir": dict(cfl=1.6, stir=(2.0, 4.5, 2e-4, 7), body=(1e-4, -5e-5)),
+    "cfl_2_discs": dict(cfl=2.0, discs=[(30.0, 20.0, 5.0)]),
     # per-node tau from eta/s (tau ~ 1.49 and ~ 0.93 at eps = 1)
     "eta_s": dict(eta_s=(0.02, 0.05)),
     "eta_s_walls_force": dict(eta_s=(0.01, 0.04), walls=True, discs=[(30.0, 20.0, 5.0)],
