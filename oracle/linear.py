@@ -25,11 +25,21 @@ import numpy as np
 from .velocity_set import velocity_set
 
 
-def stream_symbol(k, cfl=1.0):
+def momentum_set(planar=False):
+    """(v, w, c1): the momenta, weights and the first-order equilibrium
+    coefficient (3 for the 3D set, 2 for the planar set)."""
+    if planar:
+        from .planar import V, W
+        return V, W, 2.0
+    v, w, _ = velocity_set()
+    return v, w, 3.0
+
+
+def stream_symbol(k, cfl=1.0, planar=False):
     """s_i(k) = sum over the 4 bilinear taps of weight * exp(-i k.offset):
     along each axis the displacement |d| = m + a has taps m and m + 1 cells
     upstream with weights 1 - a and a."""
-    v, _, _ = velocity_set()
+    v, _, _ = momentum_set(planar)
     s = np.zeros(v.shape[0], np.complex128)
     for i in range(v.shape[0]):
         f = 1.0 + 0j
@@ -42,20 +52,20 @@ def stream_symbol(k, cfl=1.0):
     return s
 
 
-def update_matrix(k, tau, cfl=1.0):
-    v, w, _ = velocity_set()
+def update_matrix(k, tau, cfl=1.0, planar=False):
+    v, w, c1 = momentum_set(planar)
     q = v.shape[0]
-    E = w[:, None] * (1.0 + 3.0 * v @ v.T)            # E_ij = w_i (1 + 3 v_i.v_j)
+    E = w[:, None] * (1.0 + c1 * v @ v.T)             # E_ij = w_i (1 + c1 v_i.v_j)
     C = np.eye(q) - (np.eye(q) - E) / tau
-    return C @ np.diag(stream_symbol(k, cfl))
+    return C @ np.diag(stream_symbol(k, cfl, planar))
 
 
-def hydrodynamic_modes(k, tau, cfl=1.0):
+def hydrodynamic_modes(k, tau, cfl=1.0, planar=False):
     """Return (lambda_shear, lambda_sound) for a wavevector k.  The shear mode
     is the eigenvector with the largest transverse momentum weight, the sound
     mode the one (Im lambda > 0) with the largest energy weight."""
-    v, _, _ = velocity_set()
-    M = update_matrix(k, tau, cfl)
+    v, _, _ = momentum_set(planar)
+    M = update_matrix(k, tau, cfl, planar)
     lam, vec = np.linalg.eig(M)
     kh = np.array([k[0], k[1], 0.0]) / np.linalg.norm(k)
     th = np.array([-kh[1], kh[0], 0.0])

@@ -35,7 +35,7 @@ class LandauError(ArithmeticError):
 # --------------------------------------------------------------------------
 # Streaming (Ch. 3, LBM procedure step 2; "linear interpolation scheme")
 # --------------------------------------------------------------------------
-def stream(F, cfl=1.0):
+def stream(F, cfl=1.0, v=None):
     """Pull-stream every population along its in-plane displacement.
 
     Population i moves by delta_i = cfl * (v_ix, v_iy) per step.  The momentum
@@ -49,8 +49,10 @@ def stream(F, cfl=1.0):
     Methods").  The lattice has one z node, so the z displacement is the
     identity.
     Borders are periodic in x and y (walls are solid nodes, and open x
-    borders overwrite their columns after the update, see `step`).
+    borders overwrite their columns after the update, see `step`).  `v`
+    (Q, 3) selects another momentum set (default: the 26 directions).
     """
+    V = globals()["V"] if v is None else v
     if not (0.0 < cfl <= 2.0):
         raise ValueError("the bilinear pull supports 0 < cfl <= 2")
     out = np.empty_like(F)
@@ -71,14 +73,17 @@ def stream(F, cfl=1.0):
 # --------------------------------------------------------------------------
 # Moments (Ch. 3, eq. energyMomentumIntegral and the T^{mu nu} matrix)
 # --------------------------------------------------------------------------
-def energy_momentum(F):
-    """T^{mu nu}(x) = sum_i F_i v_i^mu v_i^nu, shape (4, 4, Ny, Nx)."""
-    return np.einsum("im,in,iyx->mnyx", VMU, VMU, F)
+def energy_momentum(F, v=None):
+    """T^{mu nu}(x) = sum_i F_i v_i^mu v_i^nu, shape (4, 4, Ny, Nx); `v`
+    selects another momentum set."""
+    vmu = VMU if v is None else four_velocity(v)
+    return np.einsum("im,in,iyx->mnyx", vmu, vmu, F)
 
 
-def charge_current(G):
+def charge_current(G, v=None):
     """J^mu(x) = sum_i G_i v_i^mu, shape (4, Ny, Nx)."""
-    return np.einsum("im,iyx->myx", VMU, G)
+    vmu = VMU if v is None else four_velocity(v)
+    return np.einsum("im,iyx->myx", vmu, G)
 
 
 def third_moment(F):
@@ -196,10 +201,11 @@ def equilibrium_G(n, u):
 # --------------------------------------------------------------------------
 # Collision (Ch. 3, eq. boltzmanneq_rel: Anderson-Witting rate p.u / tau_R)
 # --------------------------------------------------------------------------
-def collision_rate(u, tau):
+def collision_rate(u, tau, v=None):
     """omega_i = p^mu u_mu / (p^0 tau) = (u^0 - u . v_i) / tau; tau is a
     number or an (Ny, Nx) array (per-node relaxation time)."""
-    return np.einsum("im,m,myx->iyx", VMU, np.diag(METRIC), u) / tau
+    vmu = VMU if v is None else four_velocity(v)
+    return np.einsum("im,m,myx->iyx", vmu, np.diag(METRIC), u) / tau
 
 
 def temperature(eps):
