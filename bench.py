@@ -113,11 +113,15 @@ print(json.dumps(dict(steps=steps, seconds=el, cells=n * n)))
 def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=None, cfl=1.0):
     c = workloads.FORCED_4096
     nx, ny = c["nx"], c["ny"]
-    lat = rlb.Lattice(nx, ny, c["tau"], cfl=cfl, full26=(layout == "full26"), eps_ref=c["eps"],
-                      n_ref=c["n"])
+    planar = layout == "planar12"
+    lat = rlb.Lattice(nx, ny, c["tau"], cfl=cfl, full26=(layout == "full26"), planar=planar,
+                      eps_ref=c["eps"], n_ref=c["n"])
     f = workloads.uniform(nx, ny, c["eps"], c["n"])
+    if planar:                             # no driving term: a seeded random flow instead
+        f = workloads.random_fields(nx, ny, seed=c["seed"], beta=0.01)
     lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
-    lat.set_stirring(c["kmin"], c["kmax"], c["amplitude"], c["seed"])
+    if not planar:
+        lat.set_stirring(c["kmin"], c["kmax"], c["amplitude"], c["seed"])
     if eta_s is not None:                  # per-node tau from eta/s instead of tau
         lat.set_relaxation_eta_s(*eta_s)
     lat.step(2)
@@ -142,7 +146,7 @@ def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=No
     # algorithmic bytes of one step-kernel launch: every population plane
     # read once and written once (2 families x q planes x 4 B each way)
     # plus the two float32 stirring-force planes read
-    bytes_per_cell = 2 * 2 * q * 4 + 2 * 4
+    bytes_per_cell = 2 * 2 * q * 4 + (0 if planar else 2 * 4)
     bytes_per_launch = bytes_per_cell * cells
     kernel_ms = kms / max(launches, 1)
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
@@ -359,6 +363,11 @@ def main():
         variants["cfl_1_25"] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms",
                                                   "bytes_per_cell", "achieved_gbs")}
         variants["cfl_1_25"]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
+        # planar (2+1) momentum set, 4096^2 seeded random flow (no driving term)
+        v = run_plain(torch, rlb, workloads, "planar12", max(a.steps // 3, 10), a.warmup)
+        variants["planar12"] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms",
+                                                  "bytes_per_cell", "achieved_gbs")}
+        variants["planar12"]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
     batched = None
     if not a.no_batch:
         batched = run_batch(torch, rlb, workloads, max(a.steps // 5, 50), 20)

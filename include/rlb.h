@@ -58,6 +58,8 @@ typedef enum {
                           /* the 17 z-mirror-folded planes (see rlb_create)   */
 #define RLB_OPEN_X  0x4u  /* open x borders: velocity inlet at x = 0,        */
                           /* pressure outlet at x = nx-1 (rlb_set_open_borders) */
+#define RLB_PLANAR  0x8u  /* planar (2+1) momentum set: 12 in-plane unit     */
+                          /* momenta, P = eps/2, c_s^2 = 1/2 (see rlb_create)  */
 
 /* Lattice parameters.
  *   nx, ny   lattice nodes (one z node); 4 <= nx, ny; ny * (nx rounded up
@@ -72,7 +74,15 @@ typedef enum {
  *            reaches two nodes and needs a periodic lattice (RLB_WALLS_Y and
  *            RLB_OPEN_X give RLB_EUNSUPPORTED); rlb_adjoint_run and
  *            rlb_column_current support cfl <= 1.
- *   flags    RLB_WALLS_Y | RLB_FULL26 | RLB_OPEN_X.
+ *   flags    RLB_WALLS_Y | RLB_FULL26 | RLB_OPEN_X | RLB_PLANAR.  RLB_PLANAR
+ *            replaces the paper's 3D momentum set (P = eps/3, c_s^2 = 1/3 on
+ *            the one-z-node lattice) by 12 in-plane momenta at 30 degrees for
+ *            particles confined to the plane (traceless T over t, x, y:
+ *            P = eps/2, c_s^2 = 1/2; equilibrium
+ *            w eps (1 - 3/2 |u|^2 + 3 u^0 u.v + 6 (u.v)^2), w n (u^0 + 2 u.v)).
+ *            It has no driving term (rlb_set_body_force / rlb_set_stirring
+ *            give RLB_EUNSUPPORTED), no open borders, no adjoint; it cannot
+ *            be combined with RLB_FULL26.
  *   eps_ref, n_ref  shifted-storage references: populations are stored as
  *            F_i - w_i eps_ref and G_i - w_i n_ref in float32 (the float32
  *            rounding then acts on the deviation only).  Any finite value is

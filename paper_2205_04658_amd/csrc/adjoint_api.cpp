@@ -51,6 +51,7 @@ rlb_status check_cfg(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
   if (lat->p.flags & RLB_OPEN_X)
     return afail(RLB_EUNSUPPORTED, "the adjoint supports periodic x borders only");
   if (lat->p.cfl > 1.0) return afail(RLB_EUNSUPPORTED, "the adjoint supports cfl <= 1 only");
+  if (lat->p.flags & RLB_PLANAR) return afail(RLB_EUNSUPPORTED, "the adjoint supports the 3D momentum set only");
   if (c->nsteps < 2 || (c->nsteps & 1)) return afail(RLB_EINVAL, "nsteps must be even and >= 2");
   if (c->checkpoint < 1) return afail(RLB_EINVAL, "checkpoint interval must be >= 1");
   if (c->objective != RLB_OBJ_CURRENT && c->objective != RLB_OBJ_DISSIPATION)

@@ -64,7 +64,12 @@ rlb_status check_params(const rlb_params* p) {
                 "cfl must be in (0, 2] (bilinear pull over at most a two-node neighbourhood)");
   if (p->cfl > 1.0 && (p->flags & (RLB_WALLS_Y | RLB_OPEN_X)))
     return fail(RLB_EUNSUPPORTED, "cfl > 1 is supported on periodic lattices (no walls, no open borders)");
-  if (p->flags & ~(RLB_WALLS_Y | RLB_FULL26 | RLB_OPEN_X)) return fail(RLB_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~(RLB_WALLS_Y | RLB_FULL26 | RLB_OPEN_X | RLB_PLANAR))
+    return fail(RLB_EINVAL, "unknown flags 0x%x", p->flags);
+  if ((p->flags & RLB_PLANAR) && (p->flags & RLB_FULL26))
+    return fail(RLB_EINVAL, "RLB_PLANAR and RLB_FULL26 select different momentum sets");
+  if ((p->flags & RLB_PLANAR) && (p->flags & RLB_OPEN_X))
+    return fail(RLB_EUNSUPPORTED, "open x borders are implemented for the 3D momentum set");
   if (!std::isfinite(p->eps_ref) || !std::isfinite(p->n_ref))
     return fail(RLB_EINVAL, "eps_ref and n_ref must be finite");
   return RLB_OK;
@@ -91,7 +96,9 @@ Workspace layout(const rlb_params* p, int Q, int64_t pitch) {
   return w;
 }
 
-int planes_of(const rlb_params* p) { return (p->flags & RLB_FULL26) ? 26 : 17; }
+int planes_of(const rlb_params* p) {
+  return (p->flags & RLB_PLANAR) ? 12 : ((p->flags & RLB_FULL26) ? 26 : 17);
+}
 
 // Bilinear tap weights per plane, quantised to multiples of 2^-24 with the
 // last weight taking the exact remainder, so the four float32 weights sum to
@@ -263,7 +270,9 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   lat->desc.row = row;
   lat->desc.pad = 0;
   lat->result = (double*)(lat->ws + w.misc_off + 128);
-  if (Q == 17) fill_taps<Dir17>(lat); else fill_taps<Dir26>(lat);
+  if (Q == 17) fill_taps<Dir17>(lat);
+  else if (Q == 12) fill_taps<DirP12>(lat);
+  else fill_taps<Dir26>(lat);
 
   rlb_status st = RLB_OK;
   // zero both state copies and the force planes: the row padding is never
@@ -358,6 +367,8 @@ rlb_status rlb_clear_obstacles(rlb_lattice* lat) {
 
 rlb_status rlb_set_body_force(rlb_lattice* lat, double fx, double fy) {
   if (rlb_status s = check_lat(lat)) return s;
+  if (lat->p.flags & RLB_PLANAR)
+    return fail(RLB_EUNSUPPORTED, "the planar momentum set has no driving term");
   if (!std::isfinite(fx) || !std::isfinite(fy)) return fail(RLB_EINVAL, "force must be finite");
   lat->fx = fx;
   lat->fy = fy;
@@ -367,6 +378,8 @@ rlb_status rlb_set_body_force(rlb_lattice* lat, double fx, double fy) {
 rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax, double amplitude,
                             uint64_t seed) {
   if (rlb_status s = check_lat(lat)) return s;
+  if (lat->p.flags & RLB_PLANAR)
+    return fail(RLB_EUNSUPPORTED, "the planar momentum set has no driving term");
   if (!std::isfinite(amplitude) || amplitude < 0.0) return fail(RLB_EINVAL, "amplitude must be finite and >= 0");
   if (amplitude == 0.0) {
     lat->stir = false;

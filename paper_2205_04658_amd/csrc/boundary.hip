@@ -187,6 +187,7 @@ static void column_go(const rlb_lattice* lat, const StepShared& sh, int x, doubl
 hipError_t launch_column_current(const rlb_lattice* lat, int x, double* out) {
   const StepShared sh = shared_of(lat);
   if (lat->Q == 17) column_go<Dir17>(lat, sh, x, out);
+  else if (lat->Q == 12) column_go<DirP12>(lat, sh, x, out);
   else column_go<Dir26>(lat, sh, x, out);
   return hipGetLastError();
 }

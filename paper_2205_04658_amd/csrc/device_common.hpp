@@ -56,6 +56,10 @@ __device__ __noinline__ double cubic_largest_root(double c2, double c1, double c
   return lam;
 }
 
+// The Newton start is the ideal-fluid energy density: for P = eps/3,
+// eps = sqrt(4 a^2 - 3 b^2) - a; for the planar set (P = eps/2),
+// eps = (sqrt(9 a^2 - 8 b^2) - a) / 2 (a = T^00, b = |T^0i|).
+template <bool PLANAR = false>
 __device__ __forceinline__ bool landau3(double T00, double T0x, double T0y,
                                         double Txx, double Txy, double Tyy,
                                         Frame& fr) {
@@ -67,8 +71,9 @@ __device__ __forceinline__ bool landau3(double T00, double T0x, double T0y,
   const double c1 = (a00 * a11 - a01 * a10) + (a00 * a22 - a02 * a20) + m12;
   const double c0 = a00 * m12 - a01 * (a10 * a22 - a12 * a20) +
                     a02 * (a10 * a21 - a11 * a20);
-  const double disc = 4.0 * T00 * T00 - 3.0 * (T0x * T0x + T0y * T0y);
-  double lam = disc > 0.0 ? sqrt(disc) - T00 : T00;
+  const double b2 = T0x * T0x + T0y * T0y;
+  const double disc = PLANAR ? 9.0 * T00 * T00 - 8.0 * b2 : 4.0 * T00 * T00 - 3.0 * b2;
+  double lam = disc > 0.0 ? (PLANAR ? 0.5 * (sqrt(disc) - T00) : sqrt(disc) - T00) : T00;
   double step = 0.0, d = 0.0;
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
@@ -119,6 +124,9 @@ __device__ __forceinline__ bool landau3(double T00, double T0x, double T0y,
 //     G_eq = w (n u^0 + 3 n (u.v)).
 // The kernels store F - w eps_ref and G - w n_ref, so the constant terms are
 // formed in float64 relative to the references before rounding.
+// Planar set (P = eps/2, circle polynomials with coefficients 1, 2, 4):
+//     F_eq = w (eps - 3/2 eps |u|^2 + 3 eps u^0 (u.v) + 6 eps (u.v)^2),
+//     G_eq = w (n u^0 + 2 n (u.v)).
 // ---------------------------------------------------------------------------
 struct EqCoef {
   float A, B, C;   // F_eq - w eps_ref = w (A + B s + C s^2), s = u.v
@@ -126,16 +134,19 @@ struct EqCoef {
 };
 
 // kappa: see dirset.hpp (float32 quadrature correction of the s, s^2 terms).
+template <bool PLANAR = false>
 __device__ __forceinline__ EqCoef eq_coef(const Frame& fr, double n,
                                           double eps_ref, double n_ref,
                                           double kappa) {
+  constexpr double cu = PLANAR ? 1.5 : 2.0, cb = PLANAR ? 3.0 : 4.0;
+  constexpr double cc = PLANAR ? 6.0 : 10.0, cg = PLANAR ? 2.0 : 3.0;
   EqCoef c;
   const double u2 = fr.ux * fr.ux + fr.uy * fr.uy;
-  c.A = (float)((fr.eps - eps_ref) - 2.0 * fr.eps * u2);
-  c.B = (float)(4.0 * kappa * fr.eps * fr.u0);
-  c.C = (float)(10.0 * kappa * fr.eps);
+  c.A = (float)((fr.eps - eps_ref) - cu * fr.eps * u2);
+  c.B = (float)(cb * kappa * fr.eps * fr.u0);
+  c.C = (float)(cc * kappa * fr.eps);
   c.Ag = (float)(n * fr.u0 - n_ref);
-  c.Bg = (float)(3.0 * kappa * n);
+  c.Bg = (float)(cg * kappa * n);
   return c;
 }
 

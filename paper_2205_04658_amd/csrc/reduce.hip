@@ -92,6 +92,10 @@ hipError_t launch_totals(const rlb_lattice* lat, const float* state,
     hipLaunchKernelGGL(totals_kernel<Dir17>, dim3(kRedBlocks), dim3(256), 0,
                        lat->stream, state, lat->p.nx, lat->p.ny, lat->row,
                        lat->partials);
+  else if (lat->Q == 12)
+    hipLaunchKernelGGL(totals_kernel<DirP12>, dim3(kRedBlocks), dim3(256), 0,
+                       lat->stream, state, lat->p.nx, lat->p.ny, lat->row,
+                       lat->partials);
   else
     hipLaunchKernelGGL(totals_kernel<Dir26>, dim3(kRedBlocks), dim3(256), 0,
                        lat->stream, state, lat->p.nx, lat->p.ny, lat->row,

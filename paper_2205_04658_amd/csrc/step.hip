@@ -95,21 +95,21 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
   });
   double T00 = a.eps_ref + (double)m00;
   double T0x = (double)m0x, T0y = (double)m0y;
-  double Txx = a.eps_ref * (1.0 / 3.0) + (double)mxx;
-  double Tyy = a.eps_ref * (1.0 / 3.0) + (double)myy;
+  double Txx = a.eps_ref * DS::cs2 + (double)mxx;
+  double Tyy = a.eps_ref * DS::cs2 + (double)myy;
   double Txy = (double)mxy;
   double J0 = a.n_ref + (double)j0, Jx = (double)jx, Jy = (double)jy;
   if constexpr (MASK) {
     if (solid) {
       T00 = a.eps_ref; T0x = 0.0; T0y = 0.0;
-      Txx = a.eps_ref * (1.0 / 3.0); Tyy = Txx; Txy = 0.0;
+      Txx = a.eps_ref * DS::cs2; Tyy = Txx; Txy = 0.0;
       J0 = a.n_ref; Jx = 0.0; Jy = 0.0;
     }
   }
 
   // 3. Landau frame and charge density
   Frame fr{0.0, 1.0, 0.0, 0.0};
-  bool ok = landau3(T00, T0x, T0y, Txx, Txy, Tyy, fr);
+  bool ok = landau3<DS::planar>(T00, T0x, T0y, Txx, Txy, Tyy, fr);
   const double n = fr.u0 * J0 - fr.ux * Jx - fr.uy * Jy;
   ok = ok && (n == n);
 
@@ -140,7 +140,7 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
     }
 
     // 4. equilibrium and collision-rate coefficients
-    const EqCoef ec = eq_coef(fr, n, a.eps_ref, a.n_ref, DS::kappa);
+    const EqCoef ec = eq_coef<DS::planar>(fr, n, a.eps_ref, a.n_ref, DS::kappa);
     const float ux = (float)fr.ux, uy = (float)fr.uy;
     // 1/tau: constant, or from eta/s at the node's temperature,
     // T ~ eps^(1/4) (tau_R = 5 (eta/s) / T with eps = 3 T^4 / pi^2)
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void init_kernel(
     atomicOr(err, ERR_LANDAU);
     fr.eps = eps_ref; fr.u0 = 1.0; fr.ux = 0.0; fr.uy = 0.0;
   }
-  const EqCoef ec = eq_coef(fr, (double)nn[i], eps_ref, n_ref, DS::kappa);
+  const EqCoef ec = eq_coef<DS::planar>(fr, (double)nn[i], eps_ref, n_ref, DS::kappa);
   const float ux = (float)fr.ux, uy = (float)fr.uy;
   static_for<0, DS::Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
@@ -394,8 +394,10 @@ template <class DS, int SM, bool MASK>
 static void by_force(int mode, int force, int ty, const TileArgs& a, int grid, hipStream_t s) {
   if (mode == MODE_FIELDS) return by_rows<DS, SM, MASK, FORCE_NONE, MODE_FIELDS>(4, a, grid, s);
   if (force == FORCE_NONE) return by_rows<DS, SM, MASK, FORCE_NONE, MODE_STEP>(ty, a, grid, s);
-  if (force == FORCE_BODY) return by_rows<DS, SM, MASK, FORCE_BODY, MODE_STEP>(ty, a, grid, s);
-  by_rows<DS, SM, MASK, FORCE_STIR, MODE_STEP>(ty, a, grid, s);
+  if constexpr (!DS::planar) {   // the planar set has no driving term (rejected on the host)
+    if (force == FORCE_BODY) return by_rows<DS, SM, MASK, FORCE_BODY, MODE_STEP>(ty, a, grid, s);
+    by_rows<DS, SM, MASK, FORCE_STIR, MODE_STEP>(ty, a, grid, s);
+  }
 }
 
 template <class DS>
@@ -432,6 +434,7 @@ hipError_t launch_tiles(int Q, int sm, bool mask, int mode, int force_mode,
     grid = std::min(grid, 8 * a.tiles_per_xcd);
   }
   if (Q == 17) by_flags<Dir17>(sm, mask, mode, force_mode, ty, a, grid, s);
+  else if (Q == 12) by_flags<DirP12>(sm, mask, mode, force_mode, ty, a, grid, s);
   else by_flags<Dir26>(sm, mask, mode, force_mode, ty, a, grid, s);
   return hipGetLastError();
 }
@@ -461,6 +464,10 @@ hipError_t launch_init(const rlb_lattice* lat, const float* eps,
   const dim3 grid((ncell + 255) / 256);
   if (lat->Q == 17)
     hipLaunchKernelGGL(init_kernel<Dir17>, grid, dim3(256), 0, lat->stream, eps,
+                       bx, by, n, dst, lat->p.nx, lat->p.ny, lat->row,
+                       lat->p.eps_ref, lat->p.n_ref, lat->err);
+  else if (lat->Q == 12)
+    hipLaunchKernelGGL(init_kernel<DirP12>, grid, dim3(256), 0, lat->stream, eps,
                        bx, by, n, dst, lat->p.nx, lat->p.ny, lat->row,
                        lat->p.eps_ref, lat->p.n_ref, lat->err);
   else

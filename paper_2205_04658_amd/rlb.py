@@ -18,6 +18,7 @@ STATUS_NAMES = ["RLB_OK", "RLB_EINVAL", "RLB_EDEVICE", "RLB_ENOMEM", "RLB_ENONFI
 WALLS_Y = 0x1
 FULL26 = 0x2
 OPEN_X = 0x4
+PLANAR = 0x8
 FIELDS = ["eps", "beta_x", "beta_y", "n", "T00", "T0x", "T0y", "Txx", "Txy", "Tyy",
           "J0", "Jx", "Jy"]
 
@@ -201,7 +202,7 @@ class Lattice:
     this object; all work goes to the torch stream current at creation."""
 
     def __init__(self, nx, ny, tau, cfl=1.0, walls=False, full26=False,
-                 eps_ref=1.0, n_ref=0.1, device=None, open_x=False, _member=None):
+                 eps_ref=1.0, n_ref=0.1, device=None, open_x=False, planar=False, _member=None):
         torch = _torch()
         if _member is not None:          # a batch member: handle owned by the batch
             batch, h = _member
@@ -210,7 +211,8 @@ class Lattice:
             self._h, self._owned, self._batch, self._keep = h, False, batch, []
             return
         self.nx, self.ny = int(nx), int(ny)
-        flags = (WALLS_Y if walls else 0) | (FULL26 if full26 else 0) | (OPEN_X if open_x else 0)
+        flags = (WALLS_Y if walls else 0) | (FULL26 if full26 else 0) | (OPEN_X if open_x else 0) \
+            | (PLANAR if planar else 0)
         self.params = Params(self.nx, self.ny, float(tau), float(cfl), flags,
                              float(eps_ref), float(n_ref))
         n = _sz()
