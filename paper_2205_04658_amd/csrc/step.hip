@@ -143,8 +143,13 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
     const EqCoef ec = eq_coef<DS::planar>(fr, n, a.eps_ref, a.n_ref, DS::kappa);
     const float ux = (float)fr.ux, uy = (float)fr.uy;
     // 1/tau: constant, or from eta/s at the node's temperature,
-    // T ~ eps^(1/4) (tau_R = 5 (eta/s) / T with eps = 3 T^4 / pi^2)
-    const float itau = a.tau_k > 0.0 ? (float)(a.tau_k * sqrt(sqrt(fr.eps))) : a.inv_tau;
+    // T ~ eps^(1/4) (tau_R = 5 (eta/s) / T with eps = 3 T^4 / pi^2); the
+    // fourth root in float32 with the hardware square root (1 ulp): the
+    // constant-tau path then pays a dozen instructions, not two float64
+    // square roots
+    const float itau = a.tau_k > 0.0
+        ? (float)a.tau_k * __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf((float)fr.eps))
+        : a.inv_tau;
     const float w0 = (float)fr.u0 * itau;
 
     // 5. driving term Phi(v) = p0 + px vx + py vy + pxx vx^2 + pxy vx vy
