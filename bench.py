@@ -200,48 +200,63 @@ def run_batch(torch, rlb, workloads, steps, warmup):
     return out
 
 
-def run_part2(torch, rlb, workloads, steps=2000, warmup=100):
+def run_part2(torch, rlb, workloads, steps=2000, warmup=100, graph_steps=100):
     """The Part II channel: 1024 x 256, velocity inlet at 0.1 (v_F = 1),
     pressure outlet, periodic lateral borders, two impurities of diameter
     0.5 um (radius 6.58 nodes) 3.38 um apart, tau 0.6, started from the
-    uniform inflow state.  Two timings of the
-    same run: steps alone, and steps with the per-step j(t) sample at the
-    column before the outlet (the workload's diagnostic).  j(omega) of the
-    recorded series is computed once at the end (timed separately)."""
+    uniform inflow state, on a stream of its own.  Timings of the same run:
+    the step kernel alone (events around each launch), steps kernel by
+    kernel, steps replayed as HIP graphs of `graph_steps` steps, and steps
+    with the per-step j(t) sample at the column before the outlet (the
+    workload's diagnostic).  j(omega) of the recorded series is computed
+    once at the end (timed separately)."""
     c = workloads.PART2
     nx, ny = c["nx"], c["ny"]
-    lat = rlb.Lattice(nx, ny, c["tau"], open_x=True, eps_ref=c["eps"], n_ref=c["n"])
-    f = workloads.uniform(nx, ny, c["eps"], c["n"])
-    f["bx"][:] = c["beta_in"]
-    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
-    lat.add_disks(np.array(workloads.part2_discs(3.38)))
-    lat.set_open_borders(c["beta_in"], 0.0, c["n"], c["eps_out"])
-    lat.step(2)
-    tune = lat.autotune(trials=5)
-    lat.step(warmup)
-    lat.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat.step(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kms, kn = lat.timing_read()
-    series = torch.zeros(steps, dtype=torch.float64, device=lat.device)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for t in range(steps):
-        lat.step(1)
-        lat.column_current(nx - 2, out=series[t:t + 1])
-    torch.cuda.synchronize()
-    wall_j = time.perf_counter() - t1
-    t2 = time.perf_counter()
-    spec = rlb.power_spectrum(series)
-    torch.cuda.synchronize()
-    wall_s = time.perf_counter() - t2
-    lat.sync()
+    stream = torch.cuda.Stream()
+
+    def wall(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    with torch.cuda.stream(stream):
+        lat = rlb.Lattice(nx, ny, c["tau"], open_x=True, eps_ref=c["eps"], n_ref=c["n"])
+        f = workloads.uniform(nx, ny, c["eps"], c["n"])
+        f["bx"][:] = c["beta_in"]
+        lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        lat.add_disks(np.array(workloads.part2_discs(3.38)))
+        lat.set_open_borders(c["beta_in"], 0.0, c["n"], c["eps_out"])
+        lat.step(2)
+        lat.autotune(trials=5)
+        lat.step(warmup)
+        lat.timing(True)
+        lat.step(steps)
+        lat.sync()
+        kms, kn = lat.timing_read()
+        lat.timing(False)
+        wall_direct = wall(lambda: lat.step(steps))
+        lat.use_graph(graph_steps)
+        lat.step(2 * graph_steps + 1)          # capture
+        wall_graph = wall(lambda: lat.step(steps))
+        lat.use_graph(0)
+        series = torch.zeros(steps, dtype=torch.float64, device=lat.device)
+
+        def with_j():
+            for t in range(steps):
+                lat.step(1)
+                lat.column_current(nx - 2, out=series[t:t + 1])
+        wall_j = wall(with_j)
+        wall_s = wall(lambda: rlb.power_spectrum(series))
+        spec = rlb.power_spectrum(series)
+        lat.sync()
+    best = min(wall_direct, wall_graph)
     out = dict(workload="channel 1024x256, inlet beta 0.1, pressure outlet, periodic y, two discs "
                         "d=0.5um (r=6.58) 3.38um apart, tau 0.6, started from the inflow state",
-               steps=steps, mlups=nx * ny * steps / wall / 1e6, ms_per_step=wall / steps * 1e3,
+               steps=steps, mlups=nx * ny * steps / best / 1e6, ms_per_step=best / steps * 1e3,
+               mlups_direct=nx * ny * steps / wall_direct / 1e6,
+               mlups_graph=nx * ny * steps / wall_graph / 1e6, graph_steps=graph_steps,
                kernel_ms=kms / max(kn, 1), bytes_per_cell=2 * 2 * lat.layout()[0] * 4 + 1,
                mlups_with_j=nx * ny * steps / wall_j / 1e6, spectrum_ms=wall_s * 1e3,
                j_mean=float(series.mean()), j_peak_bin=int(spec[1:].argmax()) + 1,

@@ -171,6 +171,19 @@ rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax,
 /* Advance nsteps >= 0 steps (asynchronous on the stream). */
 rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps);
 
+/* Replay the kernels of steps_per_graph consecutive steps (the stirring
+ * draw and synthesis, the step, the open borders) as one HIP graph, for
+ * lattices small enough that launch overhead shows.  0 (the default) turns
+ * graphs off; otherwise steps_per_graph is even, 2..4096.  rlb_step uses
+ * the graph only on a non-null stream, with kernel timing off and for at
+ * least steps_per_graph steps (plus one if the current state is the second
+ * copy); the rest runs kernel by kernel.  Results are bitwise those of
+ * direct launches.  The graph is captured on first use and again whenever
+ * a setting its kernels take by value changes (force, stirring, tau,
+ * eta/s, open borders, obstacles, launch shape, stream).  EINVAL for an
+ * odd or out-of-range count. */
+rlb_status rlb_use_graph(rlb_lattice* lat, int32_t steps_per_graph);
+
 /* Write the fields selected by field_mask (bits of RLB_FIELD_*) to d_out as
  * consecutive float32 planes [k][ny][nx] in increasing field order. */
 rlb_status rlb_read_fields(rlb_lattice* lat, uint32_t field_mask, float* d_out);

@@ -299,8 +299,17 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   return RLB_OK;
 }
 
+static void drop_lattice_graph(rlb_lattice* lat) {
+  if (lat->exec) (void)hipGraphExecDestroy(lat->exec);
+  if (lat->graph) (void)hipGraphDestroy(lat->graph);
+  lat->exec = nullptr;
+  lat->graph = nullptr;
+  lat->graph_valid = false;
+}
+
 rlb_status rlb_destroy(rlb_lattice* lat) {
   if (!lat) return RLB_OK;
+  drop_lattice_graph(lat);
   if (lat->ev[0][0]) {
     for (int i = 0; i < kEvRing; ++i)
       for (int j = 0; j < 2; ++j)
@@ -431,34 +440,101 @@ rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax, double a
   return RLB_OK;
 }
 
+// Everything the kernels of one step capture by value: a graph is valid for
+// the configuration it was captured with.
+static void graph_key(const rlb_lattice* lat, double* k) {
+  int i = 0;
+  const int force = lat->stir ? FORCE_STIR : ((lat->fx != 0.0 || lat->fy != 0.0) ? FORCE_BODY : FORCE_NONE);
+  k[i++] = force; k[i++] = lat->fx; k[i++] = lat->fy; k[i++] = lat->stir;
+  k[i++] = lat->kmin; k[i++] = lat->kmax; k[i++] = lat->amp; k[i++] = (double)lat->seed;
+  k[i++] = lat->nmodes; k[i++] = lat->K; k[i++] = lat->p.tau; k[i++] = lat->tau_k;
+  k[i++] = lat->open.bx; k[i++] = lat->open.by; k[i++] = lat->open.n_in; k[i++] = lat->open.eps_out;
+  k[i++] = lat->shape.tile_rows; k[i++] = lat->shape.grid_per_cu; k[i++] = lat->shape.strip;
+  k[i++] = lat->any_solid; k[i++] = (double)(uintptr_t)lat->stream;
+  while (i < 24) k[i++] = 0.0;
+}
+
+// The kernels of one step from state copy `parity` (stirring draw, row
+// series and synthesis; the step; the open borders of the new state).
+static hipError_t launch_one_step(rlb_lattice* lat, const StirArgs& sa, int force, int parity,
+                                  int slot) {
+  hipError_t e = hipSuccess;
+  if (lat->stir) {
+    if ((e = launch_stir_draw(sa, -1, lat->stream)) != hipSuccess) return e;
+    if ((e = launch_stir_table(sa, lat->stream)) != hipSuccess) return e;
+    if ((e = launch_stir_synth(sa, lat->stream)) != hipSuccess) return e;
+  }
+  if (slot >= 0 && (e = hipEventRecord(lat->ev[slot][0], lat->stream)) != hipSuccess) return e;
+  const int mode = step_mode(lat);
+  if ((e = launch_step(lat, mode, force, parity, nullptr, 0)) != hipSuccess) return e;
+  if (slot >= 0 && (e = hipEventRecord(lat->ev[slot][1], lat->stream)) != hipSuccess) return e;
+  if ((lat->p.flags & RLB_OPEN_X) && mode == MODE_STEP)   // borders not set by the step
+    e = launch_open_borders(lat, lat->state[parity ^ 1]);
+  return e;
+}
+
 rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps) {
   if (rlb_status s = check_lat(lat)) return s;
   if (nsteps < 0) return fail(RLB_EINVAL, "nsteps must be >= 0");
   if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: step it with rlb_batch_step");
   const int force = lat->stir ? FORCE_STIR : ((lat->fx != 0.0 || lat->fy != 0.0) ? FORCE_BODY : FORCE_NONE);
   const StirArgs sa = stir_args(lat);
-  for (int64_t t = 0; t < nsteps; ++t) {
-    if (lat->stir) {
-      HIP_TRY(launch_stir_draw(sa, -1, lat->stream), "stirring draw");
-      HIP_TRY(launch_stir_table(sa, lat->stream), "stirring table");
-      HIP_TRY(launch_stir_synth(sa, lat->stream), "stirring synthesis");
-    }
-    int slot = 0;
+  auto direct = [&]() -> rlb_status {
+    int slot = -1;
     if (lat->timing) {
       slot = (int)(lat->step % kEvRing);
       if (rlb_status s = drain_event(lat, slot)) return s;
-      HIP_TRY(hipEventRecord(lat->ev[slot][0], lat->stream), "event record");
     }
-    HIP_TRY(launch_step(lat, MODE_STEP, force, lat->cur, nullptr, 0), "step kernel");
-    if (lat->timing) {
-      HIP_TRY(hipEventRecord(lat->ev[slot][1], lat->stream), "event record");
-      lat->ev_pending |= 1u << slot;
-    }
+    HIP_TRY(launch_one_step(lat, sa, force, lat->cur, slot), "step");
+    if (slot >= 0) lat->ev_pending |= 1u << slot;
     lat->cur ^= 1;
-    if (lat->p.flags & RLB_OPEN_X)
-      HIP_TRY(launch_open_borders(lat, lat->state[lat->cur]), "open borders");
     lat->step += 1;
+    return RLB_OK;
+  };
+  int64_t left = nsteps;
+  const int K = lat->graph_steps;
+  if (K > 0 && !lat->timing && lat->stream != nullptr && left >= K + lat->cur) {
+    if (lat->cur == 1) {   // replays start from the first copy
+      if (rlb_status s = direct()) return s;
+      --left;
+    }
+    double key[24];
+    graph_key(lat, key);
+    if (lat->graph_valid && std::memcmp(key, lat->graph_key, sizeof key) != 0) drop_lattice_graph(lat);
+    if (!lat->graph_valid) {
+      HIP_TRY(hipStreamBeginCapture(lat->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+      hipError_t e = hipSuccess;
+      for (int k = 0; k < K && e == hipSuccess; ++k) e = launch_one_step(lat, sa, force, k & 1, -1);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(lat->stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+      }
+      lat->graph = g;
+      HIP_TRY(hipGraphInstantiate(&lat->exec, lat->graph, nullptr, nullptr, 0), "graph instantiate");
+      lat->graph_valid = true;
+      std::memcpy(lat->graph_key, key, sizeof key);
+    }
+    while (left >= K) {
+      HIP_TRY(hipGraphLaunch(lat->exec, lat->stream), "graph launch");
+      lat->step += K;   // K is even: the current copy is again the first
+      left -= K;
+    }
   }
+  while (left > 0) {
+    if (rlb_status s = direct()) return s;
+    --left;
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_use_graph(rlb_lattice* lat, int32_t steps_per_graph) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (steps_per_graph < 0 || (steps_per_graph & 1) || steps_per_graph > 4096)
+    return fail(RLB_EINVAL, "steps_per_graph must be 0 or even in [2, 4096]");
+  if (steps_per_graph != lat->graph_steps) drop_lattice_graph(lat);
+  lat->graph_steps = steps_per_graph;
   return RLB_OK;
 }
 
@@ -747,7 +823,7 @@ rlb_status rlb_autotune(rlb_lattice* lat, int32_t trials, double* h_ms, int32_t 
   const LaunchShape best = lat->shape;
   auto run = [&](int n) -> hipError_t {
     for (int i = 0; i < n; ++i) {   // reads the current copy, writes the other: state unchanged
-      hipError_t e = launch_step(lat, MODE_STEP, force, lat->cur, nullptr, 0);
+      hipError_t e = launch_step(lat, step_mode(lat), force, lat->cur, nullptr, 0);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;

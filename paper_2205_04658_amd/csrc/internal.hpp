@@ -26,8 +26,9 @@ enum : uint32_t { ERR_LANDAU = 1u, ERR_NONFINITE = 2u };
 
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
-// Step-kernel modes.
-enum StepMode : int { MODE_STEP = 0, MODE_FIELDS = 1 };
+// Step-kernel modes: a step, the field read-out, or a step that also sets
+// the open x borders of the new state (velocity inlet, pressure outlet).
+enum StepMode : int { MODE_STEP = 0, MODE_FIELDS = 1, MODE_OPEN = 2 };
 // Force modes: none, uniform body force, body force + k-shell stirring.
 enum ForceMode : int { FORCE_NONE = 0, FORCE_BODY = 1, FORCE_STIR = 2 };
 
@@ -39,6 +40,8 @@ struct StepShared {
   double tau_k;            // > 0: per-node 1/tau = tau_k * eps^(1/4) (eta/s relaxation)
   double eps_ref, n_ref;
   float fx, fy;           // uniform body force
+  double o_bx, o_by, o_n; // open borders: inlet 3-velocity and charge density
+  double o_eps;           // open borders: outlet energy density
   uint32_t* err;          // sticky device error word
   uint32_t field_mask;    // MODE_FIELDS selection
 };
@@ -190,6 +193,13 @@ struct rlb_lattice {
   double timed_ms;
   hipEvent_t ev[16][2];   // ring of (start, end) pairs
   uint32_t ev_pending;
+  // graph replay of graph_steps steps (0 = off); the graph captures its
+  // kernels' arguments by value, so it is tied to the configuration key
+  int graph_steps;
+  bool graph_valid;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  double graph_key[24];
   // saved-state header staging
   alignas(64) unsigned char header[256];
 };
@@ -213,6 +223,10 @@ int tiles_of(int nx, int ny, int tile_rows);
 std::vector<LaunchShape> launch_candidates(int Q);
 hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode,
                        int parity, float* fields, uint32_t field_mask);
+// The mode of a step of this lattice: MODE_OPEN when the open borders can be
+// set inside the step kernel (the outlet column and the one before it share
+// a 64-node tile, i.e. nx % 64 != 1), else MODE_STEP.
+int step_mode(const rlb_lattice* lat);
 SpectralLayout spectral_layout(int nx, int ny, int kmax);
 hipError_t launch_spectrum(rlb_lattice* lat, int kmax, double kcut, double* out, double* acc,
                            char* ws);

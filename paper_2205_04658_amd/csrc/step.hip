@@ -23,6 +23,71 @@
 
 namespace rlb {
 
+// Open x borders of the new state, set by the waves that hold them (Ch. 6,
+// "Model and Methods": a fixed velocity enters along the inflow border):
+//   * velocity inlet, column 0: equilibrium at the prescribed 3-velocity and
+//     charge density, with the energy density of column 1;
+//   * pressure outlet, column nx-1: equilibrium at the prescribed energy
+//     density, with the velocity and charge density of column nx-2.
+// The adjacent column's frame comes from Landau matching of the moments of
+// its new (post-collision) populations `fo`, `go`, which the neighbouring
+// lane has just stored; the border lane then overwrites its own store.
+// Moments in float32 in plane order, references added in float64.  Needs
+// columns nx-2 and nx-1 in one 64-node tile (nx % 64 != 1; otherwise the
+// borders are set by a kernel of their own after the step).
+template <class DS>
+__device__ __forceinline__ void open_borders(const StepShared& a, int x, int nx,
+                                             const float (&fo)[DS::Q], const float (&go)[DS::Q],
+                                             float* __restrict__ dst, int64_t rs, uint32_t cs) {
+  constexpr int Q = DS::Q;
+  const int base = x & ~63;
+  if (base != 0 && base + 63 < nx - 1) return;   // tile holds neither border (wave-uniform)
+  float m00 = 0, m0x = 0, m0y = 0, mxx = 0, mxy = 0, myy = 0, j0 = 0, jx = 0, jy = 0;
+  static_for<0, Q>([&](auto P) {
+    constexpr int p = decltype(P)::value;
+    constexpr double vx = DS::vx[p], vy = DS::vy[p];
+    m00 += fo[p];
+    j0 += go[p];
+    if constexpr (vx != 0.0) { m0x += (float)vx * fo[p]; jx += (float)vx * go[p]; mxx += (float)(vx * vx) * fo[p]; }
+    if constexpr (vy != 0.0) { m0y += (float)vy * fo[p]; jy += (float)vy * go[p]; myy += (float)(vy * vy) * fo[p]; }
+    if constexpr (vx != 0.0 && vy != 0.0) mxy += (float)(vx * vy) * fo[p];
+  });
+  // border lanes take the moments of the adjacent column's lane
+  const int lane = x & 63;
+  const int from = x == 0 ? 1 : (lane > 0 ? lane - 1 : 0);
+  m00 = __shfl(m00, from, 64); m0x = __shfl(m0x, from, 64); m0y = __shfl(m0y, from, 64);
+  mxx = __shfl(mxx, from, 64); mxy = __shfl(mxy, from, 64); myy = __shfl(myy, from, 64);
+  j0 = __shfl(j0, from, 64); jx = __shfl(jx, from, 64); jy = __shfl(jy, from, 64);
+  if (x != 0 && x != nx - 1) return;
+  const double T00 = a.eps_ref + (double)m00;
+  const double Txx = a.eps_ref * (1.0 / 3.0) + (double)mxx;
+  const double Tyy = a.eps_ref * (1.0 / 3.0) + (double)myy;
+  Frame fr{a.eps_ref, 1.0, 0.0, 0.0};
+  if (!landau3(T00, (double)m0x, (double)m0y, Txx, (double)mxy, Tyy, fr)) {
+    atomicOr(a.err, ERR_LANDAU);
+    fr = Frame{a.eps_ref, 1.0, 0.0, 0.0};
+  }
+  Frame b;
+  double n;
+  if (x == 0) {
+    frame_from_beta(fr.eps, a.o_bx, a.o_by, b);   // |beta| < 1 checked on the host
+    n = a.o_n;
+  } else {
+    b = Frame{a.o_eps, fr.u0, fr.ux, fr.uy};
+    n = fr.u0 * (a.n_ref + (double)j0) - fr.ux * (double)jx - fr.uy * (double)jy;
+  }
+  const EqCoef ec = eq_coef(b, n, a.eps_ref, a.n_ref, DS::kappa);
+  const float ux = (float)b.ux, uy = (float)b.uy;
+  static_for<0, Q>([&](auto P) {
+    constexpr int p = decltype(P)::value;
+    constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
+    constexpr float w = DS::w32[p];
+    const float s = ux * vx + uy * vy;
+    stp<p>(dst, rs, cs, w * (ec.A + s * (ec.B + s * ec.C)));
+    stp<Q + p>(dst, rs, cs, w * (ec.Ag + s * ec.Bg));
+  });
+}
+
 template <class DS, int SM, bool MASK, int FORCE, int MODE>
 __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc& L,
                                             const float* __restrict__ src,
@@ -54,7 +119,7 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
   });
 
   float Fsx = 0.0f, Fsy = 0.0f;   // stirring force, loaded with the populations
-  if constexpr (FORCE == FORCE_STIR && MODE == MODE_STEP) {
+  if constexpr (FORCE == FORCE_STIR && MODE != MODE_FIELDS) {
     const gfloat* fr = (const gfloat*)L.force + (int64_t)y * row;
     Fsx = fr[x];
     Fsy = fr[L.pitch + x];
@@ -129,110 +194,125 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
     }
     return;
   } else {
+    float fo[Q], go[Q];   // the stored values (open borders only)
     if (!ok) {   // no rest frame: flag it and leave the node uncollided
       atomicOr(a.err, ERR_LANDAU);
       static_for<0, Q>([&](auto P) {
         constexpr int p = decltype(P)::value;
         stp<p>(dst, rs, cs, f[p]);
         stp<Q + p>(dst, rs, cs, g[p]);
+        if constexpr (MODE == MODE_OPEN) {
+          fo[p] = f[p];
+          go[p] = g[p];
+        }
       });
-      return;
-    }
+    } else {
+      // 4. equilibrium and collision-rate coefficients
+      const EqCoef ec = eq_coef<DS::planar>(fr, n, a.eps_ref, a.n_ref, DS::kappa);
+      const float ux = (float)fr.ux, uy = (float)fr.uy;
+      // 1/tau: constant, or from eta/s at the node's temperature,
+      // T ~ eps^(1/4) (tau_R = 5 (eta/s) / T with eps = 3 T^4 / pi^2); the
+      // fourth root in float32 with the hardware square root (1 ulp): the
+      // constant-tau path then pays a dozen instructions, not two float64
+      // square roots
+      const float itau = a.tau_k > 0.0
+          ? (float)a.tau_k * __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf((float)fr.eps))
+          : a.inv_tau;
+      const float w0 = (float)fr.u0 * itau;
 
-    // 4. equilibrium and collision-rate coefficients
-    const EqCoef ec = eq_coef<DS::planar>(fr, n, a.eps_ref, a.n_ref, DS::kappa);
-    const float ux = (float)fr.ux, uy = (float)fr.uy;
-    // 1/tau: constant, or from eta/s at the node's temperature,
-    // T ~ eps^(1/4) (tau_R = 5 (eta/s) / T with eps = 3 T^4 / pi^2); the
-    // fourth root in float32 with the hardware square root (1 ulp): the
-    // constant-tau path then pays a dozen instructions, not two float64
-    // square roots
-    const float itau = a.tau_k > 0.0
-        ? (float)a.tau_k * __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf((float)fr.eps))
-        : a.inv_tau;
-    const float w0 = (float)fr.u0 * itau;
-
-    // 5. driving term Phi(v) = p0 + px vx + py vy + pxx vx^2 + pxy vx vy
-    //    + pyy vy^2 (vz^2 = 1 - vx^2 - vy^2 folded in)
-    float p0 = 0, px = 0, py = 0, pxx = 0, pxy = 0, pyy = 0;
-    if constexpr (FORCE != FORCE_NONE) {
-      float Fx = a.fx, Fy = a.fy;
-      if constexpr (FORCE == FORCE_STIR) {
-        Fx += Fsx;
-        Fy += Fsy;
+      // 5. driving term Phi(v) = p0 + px vx + py vy + pxx vx^2 + pxy vx vy
+      //    + pyy vy^2 (vz^2 = 1 - vx^2 - vy^2 folded in)
+      float p0 = 0, px = 0, py = 0, pxx = 0, pxy = 0, pyy = 0;
+      if constexpr (FORCE != FORCE_NONE) {
+        float Fx = a.fx, Fy = a.fy;
+        if constexpr (FORCE == FORCE_STIR) {
+          Fx += Fsx;
+          Fy += Fsy;
+        }
+        float q3xxx = 0, q3xxy = 0, q3xyy = 0, q3yyy = 0, q3xzz = 0, q3yzz = 0;
+        static_for<0, Q>([&](auto P) {
+          constexpr int p = decltype(P)::value;
+          if constexpr (DS::opp[p] > p) {   // third moments are odd
+            constexpr double vx = DS::vx[p], vy = DS::vy[p], vz2 = DS::vz2[p];
+            if constexpr (vx != 0.0) {
+              q3xxx += (float)(vx * vx * vx) * df[p];
+              if constexpr (vz2 != 0.0) q3xzz += (float)(vx * vz2) * df[p];
+            }
+            if constexpr (vy != 0.0) {
+              q3yyy += (float)(vy * vy * vy) * df[p];
+              if constexpr (vz2 != 0.0) q3yzz += (float)(vy * vz2) * df[p];
+            }
+            if constexpr (vx != 0.0 && vy != 0.0) {
+              q3xxy += (float)(vx * vx * vy) * df[p];
+              q3xyy += (float)(vx * vy * vy) * df[p];
+            }
+          }
+        });
+        const float M0 = (float)T00, M1x = (float)T0x, M1y = (float)T0y;
+        const float Qxx = Fx * q3xxx + Fy * q3xxy;
+        const float Qxy = Fx * q3xxy + Fy * q3xyy;
+        const float Qyy = Fx * q3xyy + Fy * q3yyy;
+        const float Qzz = Fx * q3xzz + Fy * q3yzz;
+        const float FM1 = Fx * M1x + Fy * M1y;
+        const float pzz = 1.25f * Qzz;
+        p0 = 0.25f * FM1 + pzz;
+        px = -0.5f * Fx * M0;
+        py = -0.5f * Fy * M0;
+        pxx = 1.25f * Qxx - 2.5f * Fx * M1x - pzz;
+        pxy = 2.5f * Qxy - 2.5f * (Fx * M1y + Fy * M1x);
+        pyy = 1.25f * Qyy - 2.5f * Fy * M1y - pzz;
       }
-      float q3xxx = 0, q3xxy = 0, q3xyy = 0, q3yyy = 0, q3xzz = 0, q3yzz = 0;
+
+      // 6. relax and drive, per opposite pair (a, b) with v_b = -v_a: the
+      //    equilibrium, rate and driving term split into even and odd parts
+      //    in s = u.v_a
       static_for<0, Q>([&](auto P) {
         constexpr int p = decltype(P)::value;
-        if constexpr (DS::opp[p] > p) {   // third moments are odd
-          constexpr double vx = DS::vx[p], vy = DS::vy[p], vz2 = DS::vz2[p];
-          if constexpr (vx != 0.0) {
-            q3xxx += (float)(vx * vx * vx) * df[p];
-            if constexpr (vz2 != 0.0) q3xzz += (float)(vx * vz2) * df[p];
+        constexpr int q = DS::opp[p];
+        constexpr float w = DS::w32[p];
+        if constexpr (q == p) {
+          const float fn = f[p] - w0 * (f[p] - w * ec.A) - w * p0;
+          const float gn = g[p] - w0 * (g[p] - w * ec.Ag);
+          stp<p>(dst, rs, cs, solid ? f[p] : fn);
+          stp<Q + p>(dst, rs, cs, solid ? g[p] : gn);
+          if constexpr (MODE == MODE_OPEN) {
+            fo[p] = solid ? f[p] : fn;
+            go[p] = solid ? g[p] : gn;
           }
-          if constexpr (vy != 0.0) {
-            q3yyy += (float)(vy * vy * vy) * df[p];
-            if constexpr (vz2 != 0.0) q3yzz += (float)(vy * vz2) * df[p];
+        } else if constexpr (q > p) {
+          constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
+          constexpr float vxx = (float)(DS::vx[p] * DS::vx[p]);
+          constexpr float vyy = (float)(DS::vy[p] * DS::vy[p]);
+          constexpr float vxy = (float)(DS::vx[p] * DS::vy[p]);
+          const float s = ux * vx + uy * vy;
+          const float t = s * itau;
+          const float e0 = w * (ec.A + ec.C * s * s), e1 = w * (ec.B * s);
+          const float g0 = w * ec.Ag, g1 = w * (ec.Bg * s);
+          const float oa = w0 - t, ob = w0 + t;
+          float fa = f[p] - oa * (f[p] - (e0 + e1));
+          float fb = f[q] - ob * (f[q] - (e0 - e1));
+          if constexpr (FORCE != FORCE_NONE) {
+            const float pe = w * (p0 + vxx * pxx + vxy * pxy + vyy * pyy);
+            const float po = w * (vx * px + vy * py);
+            fa -= pe + po;
+            fb -= pe - po;
           }
-          if constexpr (vx != 0.0 && vy != 0.0) {
-            q3xxy += (float)(vx * vx * vy) * df[p];
-            q3xyy += (float)(vx * vy * vy) * df[p];
+          const float ga = g[p] - oa * (g[p] - (g0 + g1));
+          const float gb = g[q] - ob * (g[q] - (g0 - g1));
+          stp<p>(dst, rs, cs, solid ? f[q] : fa);
+          stp<q>(dst, rs, cs, solid ? f[p] : fb);
+          stp<Q + p>(dst, rs, cs, solid ? g[q] : ga);
+          stp<Q + q>(dst, rs, cs, solid ? g[p] : gb);
+          if constexpr (MODE == MODE_OPEN) {
+            fo[p] = solid ? f[q] : fa;
+            fo[q] = solid ? f[p] : fb;
+            go[p] = solid ? g[q] : ga;
+            go[q] = solid ? g[p] : gb;
           }
         }
       });
-      const float M0 = (float)T00, M1x = (float)T0x, M1y = (float)T0y;
-      const float Qxx = Fx * q3xxx + Fy * q3xxy;
-      const float Qxy = Fx * q3xxy + Fy * q3xyy;
-      const float Qyy = Fx * q3xyy + Fy * q3yyy;
-      const float Qzz = Fx * q3xzz + Fy * q3yzz;
-      const float FM1 = Fx * M1x + Fy * M1y;
-      const float pzz = 1.25f * Qzz;
-      p0 = 0.25f * FM1 + pzz;
-      px = -0.5f * Fx * M0;
-      py = -0.5f * Fy * M0;
-      pxx = 1.25f * Qxx - 2.5f * Fx * M1x - pzz;
-      pxy = 2.5f * Qxy - 2.5f * (Fx * M1y + Fy * M1x);
-      pyy = 1.25f * Qyy - 2.5f * Fy * M1y - pzz;
     }
-
-    // 6. relax and drive, per opposite pair (a, b) with v_b = -v_a: the
-    //    equilibrium, rate and driving term split into even and odd parts
-    //    in s = u.v_a
-    static_for<0, Q>([&](auto P) {
-      constexpr int p = decltype(P)::value;
-      constexpr int q = DS::opp[p];
-      constexpr float w = DS::w32[p];
-      if constexpr (q == p) {
-        const float fn = f[p] - w0 * (f[p] - w * ec.A) - w * p0;
-        const float gn = g[p] - w0 * (g[p] - w * ec.Ag);
-        stp<p>(dst, rs, cs, solid ? f[p] : fn);
-        stp<Q + p>(dst, rs, cs, solid ? g[p] : gn);
-      } else if constexpr (q > p) {
-        constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
-        constexpr float vxx = (float)(DS::vx[p] * DS::vx[p]);
-        constexpr float vyy = (float)(DS::vy[p] * DS::vy[p]);
-        constexpr float vxy = (float)(DS::vx[p] * DS::vy[p]);
-        const float s = ux * vx + uy * vy;
-        const float t = s * itau;
-        const float e0 = w * (ec.A + ec.C * s * s), e1 = w * (ec.B * s);
-        const float g0 = w * ec.Ag, g1 = w * (ec.Bg * s);
-        const float oa = w0 - t, ob = w0 + t;
-        float fa = f[p] - oa * (f[p] - (e0 + e1));
-        float fb = f[q] - ob * (f[q] - (e0 - e1));
-        if constexpr (FORCE != FORCE_NONE) {
-          const float pe = w * (p0 + vxx * pxx + vxy * pxy + vyy * pyy);
-          const float po = w * (vx * px + vy * py);
-          fa -= pe + po;
-          fb -= pe - po;
-        }
-        const float ga = g[p] - oa * (g[p] - (g0 + g1));
-        const float gb = g[q] - ob * (g[q] - (g0 - g1));
-        stp<p>(dst, rs, cs, solid ? f[q] : fa);
-        stp<q>(dst, rs, cs, solid ? f[p] : fb);
-        stp<Q + p>(dst, rs, cs, solid ? g[q] : ga);
-        stp<Q + q>(dst, rs, cs, solid ? g[p] : gb);
-      }
-    });
+    if constexpr (MODE == MODE_OPEN) open_borders<DS>(a, x, nx, fo, go, dst, rs, cs);
   }
 }
 
@@ -356,6 +436,10 @@ StepShared shared_of(const rlb_lattice* lat) {
   a.n_ref = lat->p.n_ref;
   a.fx = (float)lat->fx;
   a.fy = (float)lat->fy;
+  a.o_bx = lat->open.bx;
+  a.o_by = lat->open.by;
+  a.o_n = lat->open.n_in;
+  a.o_eps = lat->open.eps_out;
   a.err = lat->err;
   a.field_mask = 0;
   return a;
@@ -384,7 +468,7 @@ static void go(const TileArgs& a, int grid, hipStream_t s) {
 // only (the autotuner's search space); everything else uses 4.
 template <class DS, int SM, bool MASK, int FORCE, int MODE>
 static void by_rows(int ty, const TileArgs& a, int grid, hipStream_t s) {
-  if constexpr (DS::Q == 17 && MODE == MODE_STEP) {
+  if constexpr (DS::Q == 17 && MODE != MODE_FIELDS) {
     switch (ty) {
       case 1: go<DS, SM, MASK, FORCE, MODE, 1>(a, grid, s); return;
       case 2: go<DS, SM, MASK, FORCE, MODE, 2>(a, grid, s); return;
@@ -398,6 +482,14 @@ static void by_rows(int ty, const TileArgs& a, int grid, hipStream_t s) {
 template <class DS, int SM, bool MASK>
 static void by_force(int mode, int force, int ty, const TileArgs& a, int grid, hipStream_t s) {
   if (mode == MODE_FIELDS) return by_rows<DS, SM, MASK, FORCE_NONE, MODE_FIELDS>(4, a, grid, s);
+  if (mode == MODE_OPEN) {   // open borders: not with the planar set or cfl > 1 (host checks)
+    if constexpr (!DS::planar && SM != SM_WIDE) {
+      if (force == FORCE_NONE) return by_rows<DS, SM, MASK, FORCE_NONE, MODE_OPEN>(ty, a, grid, s);
+      if (force == FORCE_BODY) return by_rows<DS, SM, MASK, FORCE_BODY, MODE_OPEN>(ty, a, grid, s);
+      by_rows<DS, SM, MASK, FORCE_STIR, MODE_OPEN>(ty, a, grid, s);
+    }
+    return;
+  }
   if (force == FORCE_NONE) return by_rows<DS, SM, MASK, FORCE_NONE, MODE_STEP>(ty, a, grid, s);
   if constexpr (!DS::planar) {   // the planar set has no driving term (rejected on the host)
     if (force == FORCE_BODY) return by_rows<DS, SM, MASK, FORCE_BODY, MODE_STEP>(ty, a, grid, s);
@@ -420,6 +512,10 @@ static void by_flags(int sm, bool mask, int mode, int force, int ty, const TileA
   }
 }
 
+int step_mode(const rlb_lattice* lat) {
+  return ((lat->p.flags & RLB_OPEN_X) && lat->p.nx % 64 != 1) ? MODE_OPEN : MODE_STEP;
+}
+
 int stream_mode(double cfl) { return cfl == 1.0 ? SM_UNIT : (cfl > 1.0 ? SM_WIDE : SM_GENERAL); }
 
 hipError_t launch_tiles(int Q, int sm, bool mask, int mode, int force_mode,
@@ -427,7 +523,7 @@ hipError_t launch_tiles(int Q, int sm, bool mask, int mode, int force_mode,
   if (a0.ntiles <= 0) return hipSuccess;
   TileArgs a = a0;
   int ty = shape.tile_rows;
-  if (!(Q == 17 && mode == MODE_STEP)) ty = 4;
+  if (!(Q == 17 && mode != MODE_FIELDS)) ty = 4;
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
   a.strip = std::max(1, shape.strip);
   int grid;
@@ -453,11 +549,11 @@ hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode, int par
   a.tile_lat = nullptr;
   a.parity = parity;
   a.tile_first = 0;
-  const int ty = (mode == MODE_STEP && lat->Q == 17) ? lat->shape.tile_rows : 4;
+  const int ty = (mode != MODE_FIELDS && lat->Q == 17) ? lat->shape.tile_rows : 4;
   a.ntiles = tiles_of(lat->p.nx, lat->p.ny, ty);
   a.fields = fields;
   LaunchShape sh = lat->shape;
-  if (mode != MODE_STEP) sh.grid_per_cu = 0;
+  if (mode == MODE_FIELDS) sh.grid_per_cu = 0;
   return launch_tiles(lat->Q, stream_mode(lat->p.cfl), lat->any_solid, mode, force_mode, a, sh,
                       lat->num_cu, lat->stream);
 }

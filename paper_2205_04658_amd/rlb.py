@@ -26,7 +26,7 @@ FIELDS = ["eps", "beta_x", "beta_y", "n", "T00", "T0x", "T0y", "Txx", "Txy", "Ty
 SYMBOLS = [
     "rlb_workspace_bytes", "rlb_create", "rlb_destroy", "rlb_init_fields",
     "rlb_set_obstacles", "rlb_add_disks", "rlb_clear_obstacles", "rlb_set_body_force",
-    "rlb_set_stirring", "rlb_step", "rlb_read_fields", "rlb_conserved", "rlb_sync",
+    "rlb_set_stirring", "rlb_step", "rlb_use_graph", "rlb_read_fields", "rlb_conserved", "rlb_sync",
     "rlb_get_step", "rlb_state_bytes", "rlb_save_state", "rlb_load_state", "rlb_layout",
     "rlb_stirring_coefficients", "rlb_stirring_field", "rlb_philox", "rlb_timing",
     "rlb_timing_read", "rlb_copy_probe", "rlb_last_error", "rlb_version",
@@ -95,6 +95,7 @@ def lib():
         "rlb_set_body_force": [_vp, _d, _d],
         "rlb_set_stirring": [_vp, _d, _d, _d, _u64],
         "rlb_step": [_vp, _i64],
+        "rlb_use_graph": [_vp, _i32],
         "rlb_read_fields": [_vp, _u32, _vp],
         "rlb_conserved": [_vp, _P(_d)],
         "rlb_sync": [_vp],
@@ -288,6 +289,10 @@ class Lattice:
     # -- stepping -----------------------------------------------------------
     def step(self, n=1):
         check(lib().rlb_step(self._h, int(n)))
+
+    def use_graph(self, steps_per_graph):
+        """Replay steps_per_graph steps as one HIP graph (0 = off, even)."""
+        check(lib().rlb_use_graph(self._h, int(steps_per_graph)))
 
     def sync(self):
         check(lib().rlb_sync(self._h))

@@ -1,7 +1,9 @@
 """Open x borders (velocity inlet, pressure outlet) and the current-density
 diagnostics on the GPU against the FP64 oracle: fields after a channel run
-with an impurity, the j(t) series at the column before the outlet and its
-spectrum, plug flow in an empty channel, and the error paths."""
+with an impurity (borders set inside the step kernel, or by a kernel of
+their own when the outlet column starts a 64-node tile), the j(t) series at
+the column before the outlet and its spectrum, plug flow in an empty
+channel, launch shapes, and the error paths."""
 import numpy as np
 import pytest
 
@@ -45,6 +47,45 @@ def test_open_channel_parity(full, cfl):
         F, G = rlb.step(F, G, TAU, cfl=cfl, solid=solid, open_x=BORDERS)
     err = compare(lat.fields(), rlb.fields(F, G, cfl=cfl, solid=solid), scales(beta=0.06, n=0.12))
     assert max(err.values()) < TOL, err
+
+
+@pytest.mark.parametrize("nx", [64, 129, 190])
+def test_open_channel_widths(nx):
+    """64: both borders in one tile; 129 = 2 * 64 + 1: the outlet column
+    starts a tile (separate border kernel); 190: ragged last tile."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    ny, steps = 24, 40
+    disc = [(nx / 3, 11.5, 3.5)]
+    f = workloads.random_fields(nx, ny, seed=31, beta=0.01)
+    lat = Lattice(nx, ny, TAU, walls=True, open_x=True)
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    lat.add_disks(np.array(disc))
+    lat.set_open_borders(*BORDERS)
+    lat.set_body_force(2e-5, 0.0)
+    lat.step(steps)
+    solid = geometry.channel_mask(nx, ny, disc)
+    F, G = oracle_start(f)
+    force = np.zeros((3, ny, nx))
+    force[0] = 2e-5
+    for _ in range(steps):
+        F, G = rlb.step(F, G, TAU, solid=solid, open_x=BORDERS, force=force)
+    err = compare(lat.fields(), rlb.fields(F, G, solid=solid), scales(beta=0.06, n=0.12))
+    assert max(err.values()) < TOL, err
+
+
+def test_open_launch_shapes_are_bitwise_identical():
+    torch = need_gpu()
+    ref = None
+    for shape in [(1, 0, 4), (2, 0, 16), (4, 4, 8), (8, 0, 1)]:
+        lat, _ = lattice()
+        lat.set_launch_shape(*shape)
+        lat.set_stirring(2, 4, 1e-4, 3)
+        lat.step(17)
+        s = lat.save_state().cpu()
+        if ref is None:
+            ref = s
+        assert torch.equal(s, ref), shape
 
 
 def test_current_series_and_spectrum():
