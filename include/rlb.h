@@ -244,6 +244,24 @@ rlb_status rlb_set_open_borders(rlb_lattice* lat, double bx, double by, double n
  * series by passing d_out + t at successive steps. */
 rlb_status rlb_column_current(rlb_lattice* lat, int32_t x, double* d_out);
 
+/* Bytes of the rlb_record_current workspace that holds `chunk` steps
+ * (1 <= chunk <= 65536): chunk * ny float64, rounded up to 256. */
+rlb_status rlb_record_workspace_bytes(const rlb_lattice* lat, int32_t chunk, size_t* bytes);
+
+/* nsteps steps that also record the current density at column x: d_series[t]
+ * = j of the state before step t+1, t = 0 .. nsteps-1.  In open channels
+ * (RLB_OPEN_X, nx % 64 != 1) and with RLB_FULL26 the step kernel writes
+ * each row's J^x while it streams and one workgroup per chunk of steps
+ * averages the rows in a fixed order: the value rlb_column_current gives
+ * for that state up to float32 rounding.  Otherwise each step is preceded
+ * by rlb_column_current (bitwise its values).  d_work: a 256-byte aligned
+ * device workspace of `bytes` (rlb_record_workspace_bytes); it holds
+ * bytes / (8 ny) steps at a time (RLB_ENOMEM below one).  Steps launch
+ * kernel by kernel, never as graphs.  Errors as rlb_step and
+ * rlb_column_current; nothing is checked past them when nsteps == 0. */
+rlb_status rlb_record_current(rlb_lattice* lat, int64_t nsteps, int32_t x, double* d_series,
+                              void* d_work, size_t bytes);
+
 /* One-sided power spectrum of the fluctuations of a float64 device series
  * s[0..n), 2 <= n <= 2^26: d_out[k] = |sum_t (s_t - mean) e^{-2 pi i k t/n}|^2
  * / n^2 for k = 0 .. n/2 (n/2 + 1 doubles; a plain sum, angles reduced

@@ -457,7 +457,7 @@ static void graph_key(const rlb_lattice* lat, double* k) {
 // The kernels of one step from state copy `parity` (stirring draw, row
 // series and synthesis; the step; the open borders of the new state).
 static hipError_t launch_one_step(rlb_lattice* lat, const StirArgs& sa, int force, int parity,
-                                  int slot) {
+                                  int slot, double* rec = nullptr, int rec_x = 0) {
   hipError_t e = hipSuccess;
   if (lat->stir) {
     if ((e = launch_stir_draw(sa, -1, lat->stream)) != hipSuccess) return e;
@@ -466,31 +466,39 @@ static hipError_t launch_one_step(rlb_lattice* lat, const StirArgs& sa, int forc
   }
   if (slot >= 0 && (e = hipEventRecord(lat->ev[slot][0], lat->stream)) != hipSuccess) return e;
   const int mode = step_mode(lat);
-  if ((e = launch_step(lat, mode, force, parity, nullptr, 0)) != hipSuccess) return e;
+  if ((e = launch_step(lat, mode, force, parity, nullptr, 0, rec, rec_x)) != hipSuccess) return e;
   if (slot >= 0 && (e = hipEventRecord(lat->ev[slot][1], lat->stream)) != hipSuccess) return e;
   if ((lat->p.flags & RLB_OPEN_X) && mode == MODE_STEP)   // borders not set by the step
     e = launch_open_borders(lat, lat->state[parity ^ 1]);
   return e;
 }
 
+// One step launched kernel by kernel (timed when timing is on).
+static rlb_status step_direct(rlb_lattice* lat, const StirArgs& sa, int force,
+                              double* rec = nullptr, int rec_x = 0) {
+  int slot = -1;
+  if (lat->timing) {
+    slot = (int)(lat->step % kEvRing);
+    if (rlb_status s = drain_event(lat, slot)) return s;
+  }
+  HIP_TRY(launch_one_step(lat, sa, force, lat->cur, slot, rec, rec_x), "step");
+  if (slot >= 0) lat->ev_pending |= 1u << slot;
+  lat->cur ^= 1;
+  lat->step += 1;
+  return RLB_OK;
+}
+
+static int force_mode(const rlb_lattice* lat) {
+  return lat->stir ? FORCE_STIR : ((lat->fx != 0.0 || lat->fy != 0.0) ? FORCE_BODY : FORCE_NONE);
+}
+
 rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps) {
   if (rlb_status s = check_lat(lat)) return s;
   if (nsteps < 0) return fail(RLB_EINVAL, "nsteps must be >= 0");
   if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: step it with rlb_batch_step");
-  const int force = lat->stir ? FORCE_STIR : ((lat->fx != 0.0 || lat->fy != 0.0) ? FORCE_BODY : FORCE_NONE);
+  const int force = force_mode(lat);
   const StirArgs sa = stir_args(lat);
-  auto direct = [&]() -> rlb_status {
-    int slot = -1;
-    if (lat->timing) {
-      slot = (int)(lat->step % kEvRing);
-      if (rlb_status s = drain_event(lat, slot)) return s;
-    }
-    HIP_TRY(launch_one_step(lat, sa, force, lat->cur, slot), "step");
-    if (slot >= 0) lat->ev_pending |= 1u << slot;
-    lat->cur ^= 1;
-    lat->step += 1;
-    return RLB_OK;
-  };
+  auto direct = [&]() { return step_direct(lat, sa, force); };
   int64_t left = nsteps;
   const int K = lat->graph_steps;
   if (K > 0 && !lat->timing && lat->stream != nullptr && left >= K + lat->cur) {
@@ -620,6 +628,47 @@ rlb_status rlb_column_current(rlb_lattice* lat, int32_t x, double* d_out) {
   if (lat->p.cfl > 1.0) return fail(RLB_EUNSUPPORTED, "the column current supports cfl <= 1");
   if (!d_out || !aligned(d_out, 8)) return fail(RLB_EINVAL, "d_out must be an 8-byte aligned device pointer");
   HIP_TRY(launch_column_current(lat, x, d_out), "column current");
+  return RLB_OK;
+}
+
+rlb_status rlb_record_workspace_bytes(const rlb_lattice* lat, int32_t chunk, size_t* bytes) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (chunk < 1 || chunk > 65536) return fail(RLB_EINVAL, "chunk must be in [1, 65536]");
+  if (!bytes) return fail(RLB_EINVAL, "bytes is null");
+  *bytes = align_up((size_t)chunk * (size_t)lat->p.ny * sizeof(double));
+  return RLB_OK;
+}
+
+rlb_status rlb_record_current(rlb_lattice* lat, int64_t nsteps, int32_t x, double* d_series,
+                              void* d_work, size_t bytes) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (nsteps < 0) return fail(RLB_EINVAL, "nsteps must be >= 0");
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: step it with rlb_batch_step");
+  if (x < 0 || x >= lat->p.nx) return fail(RLB_EINVAL, "column %d outside [0, %d)", x, lat->p.nx);
+  if (lat->p.cfl > 1.0) return fail(RLB_EUNSUPPORTED, "the column current supports cfl <= 1");
+  if (nsteps == 0) return RLB_OK;
+  if (!d_series || !aligned(d_series, 8))
+    return fail(RLB_EINVAL, "d_series must be an 8-byte aligned device pointer");
+  if (!d_work || !aligned(d_work, 256)) return fail(RLB_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  const size_t row_bytes = (size_t)lat->p.ny * sizeof(double);
+  const int64_t chunk = (int64_t)std::min<size_t>(bytes / row_bytes, 65536);
+  if (chunk < 1) return fail(RLB_ENOMEM, "record workspace has %zu bytes, needs at least %zu", bytes, row_bytes);
+  const int force = force_mode(lat);
+  const StirArgs sa = stir_args(lat);
+  if (!records_current(lat)) {   // record with the column kernel before each step
+    for (int64_t t = 0; t < nsteps; ++t) {
+      HIP_TRY(launch_column_current(lat, x, d_series + t), "column current");
+      if (rlb_status s = step_direct(lat, sa, force)) return s;
+    }
+    return RLB_OK;
+  }
+  double* rows = (double*)d_work;
+  for (int64_t t0 = 0; t0 < nsteps; t0 += chunk) {
+    const int64_t cnt = std::min(chunk, nsteps - t0);
+    for (int64_t i = 0; i < cnt; ++i)
+      if (rlb_status s = step_direct(lat, sa, force, rows + i * lat->p.ny, x)) return s;
+    HIP_TRY(launch_row_means(rows, lat->p.ny, (int)cnt, d_series + t0, lat->stream), "row means");
+  }
   return RLB_OK;
 }
 
@@ -819,7 +868,7 @@ rlb_status rlb_get_launch_shape(const rlb_lattice* lat, int32_t* tile_rows, int3
 rlb_status rlb_autotune(rlb_lattice* lat, int32_t trials, double* h_ms, int32_t max_results) {
   if (rlb_status s = check_lat(lat)) return s;
   if (trials < 1 || trials > 1000) return fail(RLB_EINVAL, "trials must be in [1, 1000]");
-  const int force = lat->stir ? FORCE_STIR : ((lat->fx != 0.0 || lat->fy != 0.0) ? FORCE_BODY : FORCE_NONE);
+  const int force = force_mode(lat);
   const LaunchShape best = lat->shape;
   auto run = [&](int n) -> hipError_t {
     for (int i = 0; i < n; ++i) {   // reads the current copy, writes the other: state unchanged

@@ -192,6 +192,27 @@ hipError_t launch_column_current(const rlb_lattice* lat, int x, double* out) {
   return hipGetLastError();
 }
 
+// One workgroup per row of `rows`: out[t] = (sum_y rows[t][y]) / ny, summed
+// in the order of the column current kernel.
+__global__ __launch_bounds__(256) void row_means_kernel(const double* __restrict__ rows, int ny,
+                                                        double* __restrict__ out) {
+  const double* r = rows + (size_t)blockIdx.x * ny;
+  double acc = 0.0;
+  for (int y = threadIdx.x; y < ny; y += blockDim.x) acc += r[y];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = ((red[0] + red[1]) + (red[2] + red[3])) / (double)ny;
+}
+
+hipError_t launch_row_means(const double* rows, int ny, int count, double* out, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(row_means_kernel, dim3(count), dim3(256), 0, st, rows, ny, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_power_spectrum(const double* s, int64_t n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(series_mean_kernel, dim3(1), dim3(256), 0, st, s, n, out);
   hipError_t e = hipGetLastError();

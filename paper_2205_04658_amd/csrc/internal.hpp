@@ -44,6 +44,8 @@ struct StepShared {
   double o_eps;           // open borders: outlet energy density
   uint32_t* err;          // sticky device error word
   uint32_t field_mask;    // MODE_FIELDS selection
+  double* rec;            // non-null (records_current): J^x of the streamed
+  int32_t rec_x;          //   populations at column rec_x written to rec[y] (row y)
 };
 
 // One lattice as the tile kernel sees it (device memory, read with scalar
@@ -222,17 +224,23 @@ int tiles_of(int nx, int ny, int tile_rows);
 // folded set).
 std::vector<LaunchShape> launch_candidates(int Q);
 hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode,
-                       int parity, float* fields, uint32_t field_mask);
+                       int parity, float* fields, uint32_t field_mask,
+                       double* rec = nullptr, int rec_x = 0);
 // The mode of a step of this lattice: MODE_OPEN when the open borders can be
 // set inside the step kernel (the outlet column and the one before it share
 // a 64-node tile, i.e. nx % 64 != 1), else MODE_STEP.
 int step_mode(const rlb_lattice* lat);
+// Whether the step kernels of this lattice can record a column's current
+// (open-channel kernels and the full set's kernels).
+bool records_current(const rlb_lattice* lat);
 SpectralLayout spectral_layout(int nx, int ny, int kmax);
 hipError_t launch_spectrum(rlb_lattice* lat, int kmax, double kcut, double* out, double* acc,
                            char* ws);
 hipError_t launch_open_borders(const rlb_lattice* lat, float* state);
 hipError_t launch_column_current(const rlb_lattice* lat, int x, double* out);
 hipError_t launch_power_spectrum(const double* s, int64_t n, double* out, hipStream_t st);
+// out[t] = (1/ny) sum_y rows[t * ny + y], t < count, fixed summation order.
+hipError_t launch_row_means(const double* rows, int ny, int count, double* out, hipStream_t st);
 hipError_t launch_init(const rlb_lattice* lat, const float* eps,
                        const float* bx, const float* by, const float* n,
                        float* dst);

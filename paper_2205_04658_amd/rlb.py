@@ -36,7 +36,7 @@ SYMBOLS = [
     "rlb_batch_set_launch_shape", "rlb_batch_get_launch_shape", "rlb_batch_autotune",
     "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
     "rlb_set_relaxation_time", "rlb_set_relaxation_eta_s", "rlb_adjoint_workspace_bytes",
-    "rlb_adjoint_run", "rlb_set_open_borders", "rlb_column_current", "rlb_power_spectrum",
+    "rlb_adjoint_run", "rlb_set_open_borders", "rlb_column_current", "rlb_record_workspace_bytes", "rlb_record_current", "rlb_power_spectrum",
     "rlb_spectrum_workspace_bytes", "rlb_energy_spectrum", "rlb_spectrum_average",
     "rlb_power_law_fit",
 ]
@@ -131,6 +131,8 @@ def lib():
         "rlb_set_relaxation_eta_s": [_vp, _d, _d],
         "rlb_set_open_borders": [_vp, _d, _d, _d, _d],
         "rlb_column_current": [_vp, _i32, _vp],
+        "rlb_record_workspace_bytes": [_vp, _i32, _P(_sz)],
+        "rlb_record_current": [_vp, _i64, _i32, _vp, _vp, _sz],
         "rlb_power_spectrum": [_vp, _i64, _vp, _vp],
         "rlb_spectrum_workspace_bytes": [_vp, _i32, _P(_sz)],
         "rlb_energy_spectrum": [_vp, _i32, _d, _vp, _vp, _vp, _sz],
@@ -412,6 +414,26 @@ class Lattice:
             raise ValueError("out must be a float64 device tensor")
         self._in(out)
         check(lib().rlb_column_current(self._h, int(x), _vp(out.data_ptr())))
+        self._out()
+        return out
+
+    def record_current(self, steps, x, out=None, chunk=1024):
+        """`steps` steps; out[t] = j at column x of the state before step
+        t + 1 (a float64 device tensor of >= steps elements; new if None).
+        The row workspace holds `chunk` steps."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(steps, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < steps \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of >= steps elements")
+        n = _sz()
+        check(lib().rlb_record_workspace_bytes(self._h, int(max(1, min(chunk, steps))),
+                                               ctypes.byref(n)))
+        work = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self._in(out, work)
+        check(lib().rlb_record_current(self._h, int(steps), int(x), _vp(out.data_ptr()),
+                                       _vp(work.data_ptr()), n.value))
         self._out()
         return out
 

@@ -114,6 +114,76 @@ def test_current_series_and_spectrum():
     assert np.abs(p - ref_o).max() < 1e-3 * ref_o.max()
 
 
+@pytest.mark.parametrize("x,chunk,full", [(NX - 2, 1024, False), (0, 7, False),
+                                          (int(DISC[0][0]), 1, False), (NX - 2, 7, True)])
+def test_record_current_equals_sample_and_step(x, chunk, full):
+    """The series the step kernel records equals the column-current kernel
+    on the same states (float32 sums in another order), in chunks of 1024,
+    7 (several chunks and a ragged one) and 1 steps, folded and full sets;
+    the states match bitwise."""
+    torch = need_gpu()
+    steps = 30
+    lat, _ = lattice(full)
+    a = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    for t in range(steps):
+        lat.column_current(x, out=a[t:t + 1])
+        lat.step(1)
+    lat2, _ = lattice(full)
+    b = lat2.record_current(steps, x, chunk=chunk)
+    assert lat2.step_count == steps
+    assert torch.equal(lat.save_state().cpu(), lat2.save_state().cpu())
+    scale = 0.12 * 0.06
+    assert (a - b).abs().max().item() < 1e-7 * scale
+    assert a.std().item() > 1e-5 * scale
+
+
+@pytest.mark.parametrize("open_x,nx", [(False, 96), (True, 129)], ids=["periodic", "tile_edge"])
+def test_record_current_without_fused_borders(open_x, nx):
+    """Periodic folded lattices and widths with nx % 64 == 1 record with the
+    column kernel before each step: bitwise the explicit loop."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+
+    def make():
+        f = workloads.random_fields(nx, 24, seed=5, beta=0.02)
+        lat = Lattice(nx, 24, TAU, open_x=open_x)
+        lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        lat.set_body_force(1e-4, 0.0)
+        return lat
+    lat = make()
+    a = torch.zeros(12, dtype=torch.float64, device="cuda")
+    for t in range(12):
+        lat.column_current(nx - 2, out=a[t:t + 1])
+        lat.step(1)
+    b = make().record_current(12, nx - 2, chunk=5)
+    assert torch.equal(a, b)
+
+
+def test_record_current_periodic_full_set():
+    """Periodic lattices of the full set record in the step kernel."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+
+    def make():
+        f = workloads.random_fields(96, 24, seed=6, beta=0.02)
+        lat = Lattice(96, 24, TAU, walls=True, full26=True)
+        lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        lat.add_disks(np.array([(50.0, 12.0, 4.0)]))
+        lat.set_stirring(1, 3, 1e-4, 8)
+        return lat
+    lat = make()
+    a = torch.zeros(20, dtype=torch.float64, device="cuda")
+    for t in range(20):
+        lat.column_current(50, out=a[t:t + 1])
+        lat.step(1)
+    lat2 = make()
+    b = lat2.record_current(20, 50, chunk=6)
+    assert torch.equal(lat.save_state().cpu(), lat2.save_state().cpu())
+    scale = 0.1 * 0.02
+    assert (a - b).abs().max().item() < 1e-7 * scale
+    assert a.std().item() > 1e-5 * scale
+
+
 def test_power_spectrum_of_a_cosine():
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import power_spectrum
