@@ -96,6 +96,19 @@ def synthesize(modes, cx, cy, nx, ny):
     return out
 
 
+def synthesize_at(modes, cx, cy, nx, ny, xs, ys):
+    """The same sum as `synthesize`, evaluated only at the nodes (xs[j],
+    ys[j]) (for lattices too large to synthesise whole).  Returns (2, J)."""
+    xs = np.asarray(xs, np.float64)
+    ys = np.asarray(ys, np.float64)
+    out = np.zeros((2, xs.size))
+    for (kx, ky), ax, ay in zip(modes, cx, cy):
+        ph = np.exp(2j * np.pi * (kx * xs / nx + ky * ys / ny))
+        out[0] += 2.0 * (ax * ph).real
+        out[1] += 2.0 * (ay * ph).real
+    return out
+
+
 class Stirring:
     """The per-step stirring field of a lattice: shell, amplitude, seed."""
 
@@ -108,3 +121,9 @@ class Stirring:
         cx, cy = stirring_coefficients(self.modes, self.seed, step,
                                        self.amplitude, self.stream)
         return synthesize(self.modes, cx, cy, self.nx, self.ny)
+
+    def field_at(self, step, xs, ys):
+        """field(step)[:, ys, xs] without synthesising the whole lattice."""
+        cx, cy = stirring_coefficients(self.modes, self.seed, step,
+                                       self.amplitude, self.stream)
+        return synthesize_at(self.modes, cx, cy, self.nx, self.ny, xs, ys)

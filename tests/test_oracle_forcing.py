@@ -73,6 +73,24 @@ def test_synthesis_equals_inverse_fft():
         assert abs(f[comp].mean()) < 1e-13
 
 
+def test_point_synthesis_equals_inverse_fft():
+    """field_at (the sum at chosen nodes, for lattices too large to
+    synthesise whole) against the inverse FFT of the Hermitian grid."""
+    nx, ny = 40, 30
+    st = forcing.Stirring(nx, ny, 2, 6, 0.2, 9)
+    cx, cy = forcing.stirring_coefficients(st.modes, 9, 4, 0.2)
+    rng = np.random.default_rng(3)
+    xs, ys = rng.integers(0, nx, 25), rng.integers(0, ny, 25)
+    got = st.field_at(4, xs, ys)
+    for comp, c in ((0, cx), (1, cy)):
+        grid = np.zeros((ny, nx), np.complex128)
+        for (kx, ky), a in zip(st.modes, c):
+            grid[ky % ny, kx % nx] += a
+            grid[(-ky) % ny, (-kx) % nx] += np.conj(a)
+        ref = (np.fft.ifft2(grid) * (nx * ny)).real
+        np.testing.assert_allclose(got[comp], ref[ys, xs], atol=1e-12)
+
+
 def test_fresh_draw_every_step():
     modes = forcing.shell_modes(7, 9)
     a = forcing.stirring_coefficients(modes, 2205, 0, 1.0)
