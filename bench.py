@@ -200,6 +200,43 @@ def run_batch(torch, rlb, workloads, steps, warmup):
     return out
 
 
+def run_part2_sweep(torch, rlb, workloads, steps=1000, warmup=50):
+    """The Part II placement sweep as one batch: six 1024 x 256 channels
+    (the single impurity, and the pair at each of the five separations
+    1.68 ... 8.39 um, 25 degrees), shared inlet/outlet and tau, one launch
+    per step over all six, replayed from a hipGraph."""
+    c = workloads.PART2
+    nx, ny = c["nx"], c["ny"]
+    placements = [workloads.part2_discs()] + [workloads.part2_discs(d) for d in c["separations_um"]]
+    B = rlb.Batch([(nx, ny)] * len(placements), c["tau"], open_x=True, eps_ref=c["eps"],
+                  n_ref=c["n"])
+    for b, discs in enumerate(placements):
+        f = workloads.uniform(nx, ny, c["eps"], c["n"])
+        f["bx"][:] = c["beta_in"]
+        B[b].init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        B[b].add_disks(np.array(discs))
+    B.set_open_borders(c["beta_in"], 0.0, c["n"], c["eps_out"])
+    B.step(2)
+    B.autotune(trials=5)
+    B.step(warmup)
+    B.sync()
+    cells = B.info()["cells"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    B.sync()
+    out = dict(channels=len(placements), cells=cells, steps=steps,
+               mlups=cells * steps / wall / 1e6, ms_per_step=wall / steps * 1e3,
+               shape=B.launch_shape())
+    out["achieved_gbs"] = (2 * 2 * B.info()["planes"] * 4 + 1) * cells / (wall / steps) / 1e9
+    B.close()
+    del B
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_part2(torch, rlb, workloads, steps=2000, warmup=100, graph_steps=100):
     """The Part II channel: 1024 x 256, velocity inlet at 0.1 (v_F = 1),
     pressure outlet, periodic lateral borders, two impurities of diameter
@@ -387,6 +424,7 @@ def main():
     part2 = None
     if not a.no_part2:
         part2 = run_part2(torch, rlb, workloads)
+        part2["sweep_batch"] = run_part2_sweep(torch, rlb, workloads)
         part2["analysis"] = run_analysis(torch, rlb, workloads)
     adjoint = None
     if not a.no_adjoint:

@@ -232,8 +232,9 @@ rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitc
  * border columns, which are overwritten), so fields read at x = 0 and
  * x = nx-1 mix the two borders.  Defaults at creation: beta = 0,
  * n_in = n_ref, eps_out = eps_ref.  RLB_EINVAL without RLB_OPEN_X, for
- * |beta| >= 1, non-finite n_in or eps_out <= 0.  Not supported in batches or
- * by rlb_adjoint_run (RLB_EUNSUPPORTED). */
+ * |beta| >= 1, non-finite n_in or eps_out <= 0, and on a batch member
+ * (members share rlb_batch_set_open_borders).  rlb_adjoint_run does not
+ * support open borders (RLB_EUNSUPPORTED). */
 rlb_status rlb_set_open_borders(rlb_lattice* lat, double bx, double by, double n_in,
                                 double eps_out);
 
@@ -374,6 +375,14 @@ rlb_status rlb_batch_member(rlb_batch* batch, int32_t b, rlb_lattice** out);
 
 /* Uniform body force of every member (Ch. 4 eq. forceTerm). */
 rlb_status rlb_batch_set_body_force(rlb_batch* batch, double fx, double fy);
+
+/* Open x borders of every member of a batch created with RLB_OPEN_X (as
+ * rlb_set_open_borders; e.g. one Part II channel per impurity placement).
+ * Such batches need nx % 64 != 1 for every member (RLB_EUNSUPPORTED at
+ * creation): the step kernel sets the borders itself.  Errors as
+ * rlb_set_open_borders; RLB_EINVAL without RLB_OPEN_X. */
+rlb_status rlb_batch_set_open_borders(rlb_batch* batch, double bx, double by, double n_in,
+                                      double eps_out);
 
 /* Advance every member nsteps steps.  All members must be at the same
  * ping-pong phase (they are unless a member was re-initialised alone):

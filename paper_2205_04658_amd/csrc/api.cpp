@@ -187,6 +187,19 @@ rlb_status accumulate_timing(rlb_lattice* lat) {
 
 void rlb::set_error_message(const char* msg) { g_err = msg; }
 
+rlb_status rlb::set_open(rlb_lattice* lat, double bx, double by, double n_in, double eps_out) {
+  if (!(lat->p.flags & RLB_OPEN_X)) return fail(RLB_EINVAL, "the lattice was created without RLB_OPEN_X");
+  if (!std::isfinite(bx) || !std::isfinite(by) || !(bx * bx + by * by < 1.0))
+    return fail(RLB_EINVAL, "inlet velocity must be finite with |beta| < 1");
+  if (!std::isfinite(n_in)) return fail(RLB_EINVAL, "inlet charge density must be finite");
+  if (!std::isfinite(eps_out) || !(eps_out > 0.0)) return fail(RLB_EINVAL, "outlet energy density must be > 0");
+  lat->open.bx = bx;
+  lat->open.by = by;
+  lat->open.n_in = n_in;
+  lat->open.eps_out = eps_out;
+  return RLB_OK;
+}
+
 extern "C" {
 
 const char* rlb_last_error(void) { return g_err.c_str(); }
@@ -608,18 +621,12 @@ rlb_status rlb_power_law_fit(const double* h_k, const double* h_y, int32_t n, do
   return RLB_OK;
 }
 
+
 rlb_status rlb_set_open_borders(rlb_lattice* lat, double bx, double by, double n_in, double eps_out) {
   if (rlb_status s = check_lat(lat)) return s;
-  if (!(lat->p.flags & RLB_OPEN_X)) return fail(RLB_EINVAL, "the lattice was created without RLB_OPEN_X");
-  if (!std::isfinite(bx) || !std::isfinite(by) || !(bx * bx + by * by < 1.0))
-    return fail(RLB_EINVAL, "inlet velocity must be finite with |beta| < 1");
-  if (!std::isfinite(n_in)) return fail(RLB_EINVAL, "inlet charge density must be finite");
-  if (!std::isfinite(eps_out) || !(eps_out > 0.0)) return fail(RLB_EINVAL, "outlet energy density must be > 0");
-  lat->open.bx = bx;
-  lat->open.by = by;
-  lat->open.n_in = n_in;
-  lat->open.eps_out = eps_out;
-  return RLB_OK;
+  if (lat->owner)
+    return fail(RLB_EINVAL, "lattice is a batch member: members share the batch's borders");
+  return set_open(lat, bx, by, n_in, eps_out);
 }
 
 rlb_status rlb_column_current(rlb_lattice* lat, int32_t x, double* d_out) {

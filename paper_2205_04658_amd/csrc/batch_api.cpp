@@ -89,13 +89,16 @@ struct BatchLayout {
 rlb_status batch_layout(const rlb_params* p, int count, const int32_t* nx, const int32_t* ny,
                         BatchLayout& L) {
   if (!p) return bfail(RLB_EINVAL, "params is null");
-  if (p->flags & RLB_OPEN_X)
-    return bfail(RLB_EUNSUPPORTED, "open x borders are not supported in batches");
   if (count < 1 || count > 65536) return bfail(RLB_EINVAL, "count must be in [1, 65536]");
   if (!nx || !ny) return bfail(RLB_EINVAL, "size arrays are null");
   size_t off = 0;
   int64_t tiles = 0;
   for (int b = 0; b < count; ++b) {
+    // open borders in a batch are set inside the step kernel, which needs the
+    // outlet column and the one before it in one 64-node tile
+    if ((p->flags & RLB_OPEN_X) && nx[b] % 64 == 1)
+      return bfail(RLB_EUNSUPPORTED, "member %d: open borders in batches need nx %% 64 != 1 (nx = %d)", b,
+                   nx[b]);
     rlb_params q = *p;
     q.nx = nx[b];
     q.ny = ny[b];
@@ -171,7 +174,8 @@ TileArgs tile_args(const rlb_batch* B, int parity) {
 }
 
 hipError_t launch_batch_step(const rlb_batch* B, int parity, bool mask, int force) {
-  return launch_tiles(B->Q, stream_mode(B->p.cfl), mask, MODE_STEP, force, tile_args(B, parity),
+  const int mode = (B->p.flags & RLB_OPEN_X) ? MODE_OPEN : MODE_STEP;
+  return launch_tiles(B->Q, stream_mode(B->p.cfl), mask, mode, force, tile_args(B, parity),
                       B->shape, B->num_cu, B->stream);
 }
 
@@ -293,6 +297,16 @@ rlb_status rlb_batch_set_body_force(rlb_batch* B, double fx, double fy) {
     m->fx = fx;
     m->fy = fy;
   }
+  return RLB_OK;
+}
+
+rlb_status rlb_batch_set_open_borders(rlb_batch* B, double bx, double by, double n_in,
+                                      double eps_out) {
+  if (rlb_status s = check_batch(B)) return s;
+  if (!(B->p.flags & RLB_OPEN_X)) return bfail(RLB_EINVAL, "the batch was created without RLB_OPEN_X");
+  for (auto* m : B->mem)
+    if (rlb_status s = set_open(m, bx, by, n_in, eps_out)) return s;
+  drop_graph(B);
   return RLB_OK;
 }
 

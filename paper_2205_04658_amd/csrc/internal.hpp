@@ -210,6 +210,8 @@ namespace rlb {
 
 // api.cpp: thread-local message returned by rlb_last_error
 void set_error_message(const char* msg);
+// api.cpp: validate and store open-border settings (no batch-member check)
+rlb_status set_open(rlb_lattice* lat, double bx, double by, double n_in, double eps_out);
 
 // step.hip
 StepShared shared_of(const rlb_lattice* lat);

@@ -32,7 +32,7 @@ SYMBOLS = [
     "rlb_timing_read", "rlb_copy_probe", "rlb_last_error", "rlb_version",
     "rlb_set_launch_shape", "rlb_get_launch_shape", "rlb_autotune",
     "rlb_batch_workspace_bytes", "rlb_batch_create", "rlb_batch_destroy", "rlb_batch_member",
-    "rlb_batch_set_body_force", "rlb_batch_step", "rlb_batch_sync", "rlb_batch_info",
+    "rlb_batch_set_body_force", "rlb_batch_set_open_borders", "rlb_batch_step", "rlb_batch_sync", "rlb_batch_info",
     "rlb_batch_set_launch_shape", "rlb_batch_get_launch_shape", "rlb_batch_autotune",
     "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
     "rlb_set_relaxation_time", "rlb_set_relaxation_eta_s", "rlb_adjoint_workspace_bytes",
@@ -118,6 +118,7 @@ def lib():
         "rlb_batch_destroy": [_vp],
         "rlb_batch_member": [_vp, _i32, _P(_vp)],
         "rlb_batch_set_body_force": [_vp, _d, _d],
+        "rlb_batch_set_open_borders": [_vp, _d, _d, _d, _d],
         "rlb_batch_step": [_vp, _i64],
         "rlb_batch_sync": [_vp],
         "rlb_batch_info": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_i64)],
@@ -531,6 +532,10 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def set_open_borders(self, bx, by, n_in, eps_out):
+        check(lib().rlb_batch_set_open_borders(self._h, float(bx), float(by), float(n_in),
+                                               float(eps_out)))
 
     def set_body_force(self, fx, fy=0.0):
         check(lib().rlb_batch_set_body_force(self._h, float(fx), float(fy)))

@@ -101,6 +101,49 @@ def test_graph_replays_with_eager_work_between():
         assert torch.equal(g.cpu(), want[b][1]), b
 
 
+OPEN_SIZES = [(96, 40), (130, 33), (64, 24)]
+OPEN_BORDERS = (0.06, 0.0, 0.12, 1.02)
+
+
+def open_member(lat, b, nx, ny):
+    f = workloads.random_fields(nx, ny, seed=200 + b, beta=0.01)
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    lat.add_disks([(nx / 3.0, ny / 2.0 - 0.5, 4.0 + b)])
+
+
+@pytest.mark.parametrize("graph", [8, 0], ids=["graph", "direct"])
+def test_open_channel_batch_equals_single_runs(graph):
+    """A batch of Part II-like channels (one impurity placement per member,
+    shared borders and body force) evolves bitwise as each channel alone,
+    including a border change between runs."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Batch, Lattice
+    want = []
+    for b, (nx, ny) in enumerate(OPEN_SIZES):
+        lat = Lattice(nx, ny, TAU, walls=True, open_x=True)
+        open_member(lat, b, nx, ny)
+        lat.set_open_borders(*OPEN_BORDERS)
+        lat.set_body_force(*FB)
+        lat.step(21)
+        lat.set_open_borders(0.08, 0.01, 0.1, 1.0)
+        lat.step(19)
+        lat.sync()
+        want.append(lat.save_state().cpu())
+    B = Batch(OPEN_SIZES, TAU, walls=True, open_x=True)
+    for b, (nx, ny) in enumerate(OPEN_SIZES):
+        open_member(B[b], b, nx, ny)
+    B.set_open_borders(*OPEN_BORDERS)
+    B.set_body_force(*FB)
+    B.use_graph(graph)
+    B.step(21)
+    B[0].fields(["eps"])
+    B.set_open_borders(0.08, 0.01, 0.1, 1.0)
+    B.step(19)
+    B.sync()
+    for b in range(len(OPEN_SIZES)):
+        assert torch.equal(B[b].save_state().cpu(), want[b]), b
+
+
 def test_autotune_does_not_advance_and_keeps_results():
     torch = need_gpu()
     B = make_batch()

@@ -229,5 +229,15 @@ def test_open_border_errors():
         lat.adjoint_run(4, 2, "current", np.zeros((0, 5)), np.zeros(0), 1e-6)
     assert e.value.status == EUNSUPPORTED
     with pytest.raises(RLBError) as e:
-        Batch([(32, 8), (40, 8)], 0.8, open_x=True)
+        Batch([(32, 8), (65, 8)], 0.8, open_x=True)       # 65 % 64 == 1
     assert e.value.status == EUNSUPPORTED
+    B = Batch([(32, 8), (40, 8)], 0.8, open_x=True)
+    with pytest.raises(RLBError) as e:
+        B[1].set_open_borders(0.1, 0.0, 0.1, 1.0)          # members share the batch's
+    assert e.value.status == EINVAL
+    with pytest.raises(RLBError) as e:
+        B.set_open_borders(1.1, 0.0, 0.1, 1.0)
+    assert e.value.status == EINVAL
+    with pytest.raises(RLBError) as e:
+        Batch([(32, 8), (40, 8)], 0.8).set_open_borders(0.1, 0.0, 0.1, 1.0)
+    assert e.value.status == EINVAL
