@@ -1,15 +1,21 @@
-"""Parity at the headline size: the forced 4096 x 4096 step, in the launch
-shape the benchmark times, checked node by node on sampled nodes.  The
-oracle cannot run a 4096^2 lattice, but the step is local: with cfl = 1 a
-node's new populations depend only on its 3 x 3 neighbourhood of the
-previous state.  So the GPU's own state before one step is gathered around
-each sampled node, the FP64 oracle steps that patch, and its centre is
-compared with the GPU's state after the step.  Samples include the lattice
-corners (periodic wrap), both sides of 64-node tile edges and random nodes."""
+"""Parity at the workloads' full sizes, in the launch shapes the benchmark
+times.  The oracle cannot run these lattices, but the step is local: with
+cfl = 1 a node's new populations depend only on its 3 x 3 neighbourhood of
+the previous state.  So the GPU's own state before one step is gathered
+around sampled nodes, the FP64 oracle steps each patch (with its solid
+nodes), and the patch centre is compared with the GPU's state after the
+step.  Samples include lattice corners (periodic wrap), both sides of
+64-node tile edges, wall rows and random nodes.  Covered: the forced 4096^2
+headline (from rest, from a random flow, full set), the forced 1024^2 run
+after 200 steps, and members of the 64-channel batch.  The adjoint at
+512 x 256 over 2000 steps is checked through properties that hold at any
+size: its gradient along a random direction against a central difference
+of its own forward objective, and invariance under the checkpoint
+interval."""
 import numpy as np
 import pytest
 
-from oracle import forcing, rlb
+from oracle import forcing, geometry, rlb
 from paper_2205_04658_amd import workloads
 from rlbtest import _folded_dirs, _full_dirs, need_gpu
 
@@ -56,6 +62,54 @@ def to_library(F, order, q, ref):
     return out
 
 
+def gather(planes, xs, ys, nx, ny, torch):
+    """(Q, M, 3, 3) float64 patches around (xs, ys), periodic."""
+    d = torch.tensor([-1, 0, 1], device=planes.device)
+    iy = (torch.tensor(ys, device=planes.device)[:, None, None] + d[None, :, None]) % ny
+    ix = (torch.tensor(xs, device=planes.device)[:, None, None] + d[None, None, :]) % nx
+    return planes[:, iy, ix].double().cpu().numpy()
+
+
+def at(planes, xs, ys, torch):
+    return planes[:, torch.tensor(ys, device=planes.device),
+                  torch.tensor(xs, device=planes.device)].double().cpu().numpy()
+
+
+def sampled_step_error(lat, xs, ys, tau, force_at, full, eps_ref, n_ref, solid=None):
+    """Take one GPU step of `lat`; return (max error F, max error G, largest
+    one-step change) of the sampled nodes against the oracle patch step."""
+    import torch
+    nx, ny = lat.nx, lat.ny
+    F0, G0 = lat.planes()
+    pf, pg = gather(F0, xs, ys, nx, ny, torch), gather(G0, xs, ys, nx, ny, torch)
+    del F0, G0
+    lat.step(1)
+    lat.sync()
+    F1, G1 = lat.planes()
+    got_f, got_g = at(F1, xs, ys, torch), at(G1, xs, ys, torch)
+    del F1, G1
+    q = pf.shape[0]
+    order = oracle_order(full)
+    err_f = err_g = change = 0.0
+    for m in range(len(xs)):
+        F = to_oracle(pf[:, m], order, eps_ref)
+        G = to_oracle(pg[:, m], order, n_ref)
+        fo = np.zeros((3, 3, 3))
+        if force_at is not None:
+            fo[0, 1, 1], fo[1, 1, 1] = force_at[0, m], force_at[1, m]
+        sp = None
+        if solid is not None:
+            sp = solid[(ys[m] + np.arange(-1, 2))[:, None] % ny, (xs[m] + np.arange(-1, 2))[None, :] % nx]
+        Fn, Gn = rlb.step(F, G, tau, force=fo, solid=sp)
+        want_f = to_library(Fn[:, 1:2, 1:2], order, q, eps_ref)[:, 0, 0]
+        want_g = to_library(Gn[:, 1:2, 1:2], order, q, n_ref)[:, 0, 0]
+        err_f = max(err_f, np.abs(got_f[:, m] - want_f).max())
+        err_g = max(err_g, np.abs(got_g[:, m] - want_g).max())
+        change = max(change, np.abs(want_f - pf[:, m, 1, 1]).max())
+    print(f"max |gpu - oracle|: F {err_f:.3e}  G {err_g:.3e}; one-step change {change:.3e}")
+    return err_f, err_g, change
+
+
 @pytest.mark.parametrize("start,full", [("rest", False), ("random", False), ("random", True)],
                          ids=["workload_rest", "random_flow", "random_flow_full26"])
 def test_headline_step_sampled(start, full):
@@ -71,40 +125,123 @@ def test_headline_step_sampled(start, full):
     del f
     stir = (C["kmin"], C["kmax"], C["amplitude"], C["seed"])
     lat.set_stirring(*stir)
-    lat.set_launch_shape(2, 0, 16) if not full else lat.set_launch_shape(4, 0, 16)
+    lat.set_launch_shape(*((4, 0, 16) if full else (2, 0, 16)))
     t0 = 20
     lat.step(t0)
     xs, ys = samples()
-    d = torch.tensor([-1, 0, 1], device="cuda")
-    iy = (torch.tensor(ys, device="cuda")[:, None, None] + d[None, :, None]) % N
-    ix = (torch.tensor(xs, device="cuda")[:, None, None] + d[None, None, :]) % N
-    F0, G0 = lat.planes()
-    pf = F0[:, iy, ix].double().cpu().numpy()     # (Q, M, 3, 3)
-    pg = G0[:, iy, ix].double().cpu().numpy()
-    del F0, G0
-    lat.step(1)
-    lat.sync()
-    F1, G1 = lat.planes()
-    cy_, cx_ = torch.tensor(ys, device="cuda"), torch.tensor(xs, device="cuda")
-    got_f = F1[:, cy_, cx_].double().cpu().numpy()  # (Q, M)
-    got_g = G1[:, cy_, cx_].double().cpu().numpy()
-    del F1, G1
-    q = pf.shape[0]
-    order = oracle_order(full)
     force = forcing.Stirring(N, N, *stir).field_at(t0, xs, ys)   # (2, M)
-    err_f = err_g = 0.0
-    scale = 0.0
-    for m in range(len(xs)):
-        F = to_oracle(pf[:, m], order, eps_ref)
-        G = to_oracle(pg[:, m], order, n_ref)
-        fo = np.zeros((3, 3, 3))
-        fo[0, 1, 1], fo[1, 1, 1] = force[0, m], force[1, m]
-        Fn, Gn = rlb.step(F, G, C["tau"], force=fo)
-        want_f = to_library(Fn[:, 1:2, 1:2], order, q, eps_ref)[:, 0, 0]
-        want_g = to_library(Gn[:, 1:2, 1:2], order, q, n_ref)[:, 0, 0]
-        err_f = max(err_f, np.abs(got_f[:, m] - want_f).max())
-        err_g = max(err_g, np.abs(got_g[:, m] - want_g).max())
-        scale = max(scale, np.abs(want_f - pf[:, m, 1, 1]).max())
-    print(f"max |gpu - oracle|: F {err_f:.3e}  G {err_g:.3e}; one-step change {scale:.3e}")
-    assert err_f < TOL and err_g < TOL, (err_f, err_g)
-    assert scale > 10 * TOL           # the step moved the sampled populations
+    ef, eg, change = sampled_step_error(lat, xs, ys, C["tau"], force, full, eps_ref, n_ref)
+    assert ef < TOL and eg < TOL, (ef, eg)
+    assert change > 10 * TOL          # the step moved the sampled populations
+
+
+def test_forced_1024_step_sampled_after_200_steps():
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    c = workloads.FORCED_1024
+    n = c["nx"]
+    lat = Lattice(n, n, c["tau"], eps_ref=c["eps"], n_ref=c["n"])
+    f = workloads.uniform(n, n, c["eps"], c["n"])
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    stir = (c["kmin"], c["kmax"], c["amplitude"], c["seed"])
+    lat.set_stirring(*stir)
+    lat.autotune(trials=2)
+    t0 = 200
+    lat.step(t0)
+    rng = np.random.default_rng(1024)
+    xs = np.concatenate([[0, n - 1, 63, 64, 511, 512], rng.integers(0, n, 42)])
+    ys = np.concatenate([[n - 1, 0, 10, 11, 512, 513], rng.integers(0, n, 42)])
+    force = forcing.Stirring(n, n, *stir).field_at(t0, xs, ys)
+    ef, eg, change = sampled_step_error(lat, xs, ys, c["tau"], force, False, c["eps"], c["n"])
+    assert ef < TOL and eg < TOL, (ef, eg)
+    assert change > 10 * TOL
+
+
+def test_batched_channels_step_sampled():
+    """The 64-channel batch (walls, discs, body force) in the autotuned
+    shape, from random flows: sampled nodes of several members, solid ones
+    included."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Batch
+    c = workloads.CHANNELS
+    lats = workloads.channel_batch(c["count"], c["seed"], c["wmin"], c["wmax"], c["hmin"],
+                                   c["hmax"], c["radius"], c["fractions"])
+    B = Batch([(d["nx"], d["ny"]) for d in lats], c["tau"], walls=True, eps_ref=c["eps"],
+              n_ref=c["n"])
+    for b, d in enumerate(lats):
+        f = workloads.random_fields(d["nx"], d["ny"], seed=300 + b, beta=0.02)
+        B[b].init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        B[b].add_disks(d["discs"])
+    B.set_body_force(c["body_force"], 0.0)
+    B.autotune(trials=1)
+    B.step(10)
+    B.sync()
+    rng = np.random.default_rng(64)
+    worst = [0.0, 0.0]
+    for b in (0, 1, 2, 31, 63):
+        lat, d = B[b], lats[b]
+        nx, ny = d["nx"], d["ny"]
+        solid = geometry.channel_mask(nx, ny, d["discs"])
+        sx, sy = np.nonzero(solid[1:-1].T)               # a few disc nodes
+        pick = rng.choice(len(sx), size=min(4, len(sx)), replace=False)
+        xs = np.concatenate([[0, nx - 1, 63, 64, 5], sx[pick], rng.integers(0, nx, 8)])
+        ys = np.concatenate([[0, ny - 1, 1, ny - 2, ny // 2], sy[pick] + 1, rng.integers(0, ny, 8)])
+        # the batch steps every member: save, step the batch once, compare
+        F0, G0 = lat.planes()
+        pf, pg = gather(F0, xs, ys, nx, ny, torch), gather(G0, xs, ys, nx, ny, torch)
+        del F0, G0
+        B.step(1)
+        B.sync()
+        F1, G1 = lat.planes()
+        got_f, got_g = at(F1, xs, ys, torch), at(G1, xs, ys, torch)
+        del F1, G1
+        order = oracle_order(False)
+        for m in range(len(xs)):
+            F = to_oracle(pf[:, m], order, c["eps"])
+            G = to_oracle(pg[:, m], order, c["n"])
+            fo = np.zeros((3, 3, 3))
+            fo[0] = c["body_force"]
+            sp = solid[(ys[m] + np.arange(-1, 2))[:, None] % ny, (xs[m] + np.arange(-1, 2))[None, :] % nx]
+            Fn, Gn = rlb.step(F, G, c["tau"], force=fo, solid=sp)
+            wf = to_library(Fn[:, 1:2, 1:2], order, 17, c["eps"])[:, 0, 0]
+            wg = to_library(Gn[:, 1:2, 1:2], order, 17, c["n"])[:, 0, 0]
+            worst[0] = max(worst[0], np.abs(got_f[:, m] - wf).max())
+            worst[1] = max(worst[1], np.abs(got_g[:, m] - wg).max())
+    print("batch max |gpu - oracle|:", worst)
+    assert worst[0] < TOL and worst[1] < TOL, worst
+
+
+def test_adjoint_full_size_directional_derivative():
+    """512 x 256 channel, 2000 steps, checkpoints every 100, 32 modes: the
+    adjoint gradient along a random direction d equals the central
+    difference (J(theta + h d) - J(theta - h d)) / 2h of the forward
+    objective to 1e-3, and the gradient does not depend on the checkpoint
+    interval."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    c = workloads.ADJOINT
+    nx, ny = c["nx"], c["ny"]
+    modes = workloads.stirring_basis(nx, ny, c["nmodes"], c["kmin"], c["kmax"], c["seed"])
+    amps = np.full(c["nmodes"], c["mode_amplitude"])
+    discs = workloads.channel_discs(nx, ny, c["radius"], c["fraction"], c["seed"])
+
+    def run(fb, tau, a, K=c["checkpoint"], grad=True):
+        lat = Lattice(nx, ny, tau, walls=True, eps_ref=c["eps"], n_ref=c["n"])
+        f = workloads.uniform(nx, ny, c["eps"], c["n"])
+        lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        lat.add_disks(discs)
+        return lat.adjoint_run(c["steps"], K, "current", modes, a, fb, grad=grad)
+
+    J, g = run(c["body_force"], c["tau"], amps)
+    J2, g2 = run(c["body_force"], c["tau"], amps, K=40)
+    assert J2 == J
+    np.testing.assert_array_equal(g2, g)
+    theta = np.concatenate([[c["body_force"], c["tau"]], amps])
+    d = np.random.default_rng(5).normal(size=theta.size) * np.abs(theta)
+    h = 1e-3
+    Jp, _ = run(*(lambda t: (t[0], t[1], t[2:]))(theta + h * d), grad=False)
+    Jm, _ = run(*(lambda t: (t[0], t[1], t[2:]))(theta - h * d), grad=False)
+    fd = (Jp - Jm) / (2 * h)
+    ad = float(g @ d)
+    print(f"directional derivative: adjoint {ad:.6e}  central difference {fd:.6e}")
+    assert abs(ad - fd) < 1e-3 * abs(fd), (ad, fd)
