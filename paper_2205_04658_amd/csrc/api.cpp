@@ -523,6 +523,7 @@ rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps) {
     graph_key(lat, key);
     if (lat->graph_valid && std::memcmp(key, lat->graph_key, sizeof key) != 0) drop_lattice_graph(lat);
     if (!lat->graph_valid) {
+      drop_lattice_graph(lat);   // a graph whose instantiation failed
       HIP_TRY(hipStreamBeginCapture(lat->stream, hipStreamCaptureModeThreadLocal), "begin capture");
       hipError_t e = hipSuccess;
       for (int k = 0; k < K && e == hipSuccess; ++k) e = launch_one_step(lat, sa, force, k & 1, -1);

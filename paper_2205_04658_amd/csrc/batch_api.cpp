@@ -361,14 +361,17 @@ rlb_status rlb_batch_step(rlb_batch* B, int64_t nsteps) {
   }
   if (graphs && left >= B->graph_steps) {
     if (!B->graph_valid) {
+      drop_graph(B);   // a graph whose instantiation failed
       BHIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal), "begin capture");
       hipError_t e = hipSuccess;
       for (int k = 0; k < B->graph_steps && e == hipSuccess; ++k)
         e = launch_batch_step(B, k & 1, mask, force);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(B->stream, &g);
-      if (e != hipSuccess || e2 != hipSuccess)
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
         return bfail(RLB_EDEVICE, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+      }
       B->graph = g;
       BHIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0), "graph instantiate");
       B->graph_valid = true;
