@@ -323,7 +323,7 @@ rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches
 
 /* Launch shape of the step kernel: tiles of 64 x tile_rows nodes (one
  * wavefront per row; tile_rows in {1, 2, 4, 8}, other than 4 only for the
- * folded layout); the grid: grid_per_cu = 0 launches one workgroup per
+ * folded layout, else RLB_EUNSUPPORTED); the grid: grid_per_cu = 0 launches one workgroup per
  * tile, k > 0 launches about k resident workgroups of 4 wavefronts per CU
  * that walk the tile list; and the tile order: a lattice's tiles are
  * visited in vertical strips `strip` tiles wide (1..65536; the last strip

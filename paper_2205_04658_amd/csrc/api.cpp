@@ -858,6 +858,8 @@ rlb_status rlb_set_launch_shape(rlb_lattice* lat, int32_t tile_rows, int32_t gri
   if (rlb_status s = check_lat(lat)) return s;
   if (!(tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8))
     return fail(RLB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
+  if (lat->Q != 17 && tile_rows != 4)
+    return fail(RLB_EUNSUPPORTED, "tile_rows != 4 needs the folded layout");
   if (grid_per_cu < 0 || grid_per_cu > 64) return fail(RLB_EINVAL, "grid_per_cu must be in [0, 64]");
   if (strip < 1 || strip > 65536) return fail(RLB_EINVAL, "strip must be in [1, 65536]");
   lat->shape = LaunchShape{tile_rows, grid_per_cu, strip};

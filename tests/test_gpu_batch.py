@@ -69,6 +69,18 @@ def test_launch_shapes_are_bitwise_identical():
                 assert torch.equal(s, ref), (ty, g, sw)
 
 
+def test_tile_heights_other_than_4_need_the_folded_layout():
+    need_gpu()
+    from paper_2205_04658_amd.rlb import EUNSUPPORTED, Lattice, RLBError
+    for kw in (dict(full26=True), dict(planar=True)):
+        lat = Lattice(64, 16, 0.7, **kw)
+        lat.set_launch_shape(4, 4, 8)
+        with pytest.raises(RLBError) as e:
+            lat.set_launch_shape(2, 0, 16)
+        assert e.value.status == EUNSUPPORTED
+        assert lat.launch_shape() == (4, 4, 8)
+
+
 @pytest.mark.parametrize("graph", [16, 0], ids=["graph", "direct"])
 def test_batch_members_equal_single_runs(graph):
     torch = need_gpu()
