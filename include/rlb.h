@@ -228,9 +228,10 @@ rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitc
  *     eps_out (pressure eps_out / 3), with the velocity and charge density
  *     of column nx-2;
  * the adjacent columns' eps, u, n from Landau matching of their stored
- * moments.  Streaming stays periodic (the wrapped values only reach the
- * border columns, which are overwritten), so fields read at x = 0 and
- * x = nx-1 mix the two borders.  Defaults at creation: beta = 0,
+ * moments (the step kernel sets the borders itself; for nx % 64 == 1 a
+ * kernel of their own follows it).  Streaming stays periodic (the wrapped
+ * values only reach the border columns, which are overwritten), so fields
+ * read at x = 0 and x = nx-1 mix the two borders.  Defaults at creation: beta = 0,
  * n_in = n_ref, eps_out = eps_ref.  RLB_EINVAL without RLB_OPEN_X, for
  * |beta| >= 1, non-finite n_in or eps_out <= 0, and on a batch member
  * (members share rlb_batch_set_open_borders).  rlb_adjoint_run does not
@@ -368,9 +369,13 @@ rlb_status rlb_batch_create(const rlb_params* p, int32_t count,
 rlb_status rlb_batch_destroy(rlb_batch* batch);
 
 /* Handle of member b for every single-lattice call except stepping and
- * forcing (rlb_init_fields, rlb_add_disks, rlb_set_obstacles,
- * rlb_read_fields, rlb_conserved, rlb_save_state, ...).  rlb_step on a
- * member returns RLB_EINVAL.  The handle is owned by the batch. */
+ * the settings the batch holds for all members (rlb_init_fields,
+ * rlb_add_disks, rlb_set_obstacles, rlb_read_fields, rlb_conserved,
+ * rlb_column_current, rlb_save_state, ...).  On a member, rlb_step,
+ * rlb_record_current, rlb_set_body_force, rlb_set_stirring,
+ * rlb_set_relaxation_time/_eta_s, rlb_set_open_borders,
+ * rlb_set_launch_shape, rlb_autotune, rlb_use_graph and rlb_timing return
+ * RLB_EINVAL.  The handle is owned by the batch. */
 rlb_status rlb_batch_member(rlb_batch* batch, int32_t b, rlb_lattice** out);
 
 /* Uniform body force of every member (Ch. 4 eq. forceTerm). */

@@ -389,6 +389,7 @@ rlb_status rlb_clear_obstacles(rlb_lattice* lat) {
 
 rlb_status rlb_set_body_force(rlb_lattice* lat, double fx, double fy) {
   if (rlb_status s = check_lat(lat)) return s;
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: use the batch's body force (rlb_batch_set_body_force)");
   if (lat->p.flags & RLB_PLANAR)
     return fail(RLB_EUNSUPPORTED, "the planar momentum set has no driving term");
   if (!std::isfinite(fx) || !std::isfinite(fy)) return fail(RLB_EINVAL, "force must be finite");
@@ -400,6 +401,7 @@ rlb_status rlb_set_body_force(rlb_lattice* lat, double fx, double fy) {
 rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax, double amplitude,
                             uint64_t seed) {
   if (rlb_status s = check_lat(lat)) return s;
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: use batches have no stirring");
   if (lat->p.flags & RLB_PLANAR)
     return fail(RLB_EUNSUPPORTED, "the planar momentum set has no driving term");
   if (!std::isfinite(amplitude) || amplitude < 0.0) return fail(RLB_EINVAL, "amplitude must be finite and >= 0");
@@ -553,6 +555,7 @@ rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps) {
 
 rlb_status rlb_use_graph(rlb_lattice* lat, int32_t steps_per_graph) {
   if (rlb_status s = check_lat(lat)) return s;
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: use the batch's graphs (rlb_batch_use_graph)");
   if (steps_per_graph < 0 || (steps_per_graph & 1) || steps_per_graph > 4096)
     return fail(RLB_EINVAL, "steps_per_graph must be 0 or even in [2, 4096]");
   if (steps_per_graph != lat->graph_steps) drop_lattice_graph(lat);
@@ -829,6 +832,7 @@ rlb_status rlb_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count, uint
 
 rlb_status rlb_timing(rlb_lattice* lat, int32_t enable) {
   if (rlb_status s = check_lat(lat)) return s;
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: use the batch's timing (rlb_batch_timing)");
   if (enable) {
     if (!lat->ev[0][0]) {
       for (int i = 0; i < kEvRing; ++i)
@@ -856,6 +860,7 @@ rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches
 rlb_status rlb_set_launch_shape(rlb_lattice* lat, int32_t tile_rows, int32_t grid_per_cu,
                                 int32_t strip) {
   if (rlb_status s = check_lat(lat)) return s;
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: use the batch's launch shape (rlb_batch_set_launch_shape)");
   if (!(tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8))
     return fail(RLB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
   if (lat->Q != 17 && tile_rows != 4)
@@ -877,6 +882,7 @@ rlb_status rlb_get_launch_shape(const rlb_lattice* lat, int32_t* tile_rows, int3
 
 rlb_status rlb_autotune(rlb_lattice* lat, int32_t trials, double* h_ms, int32_t max_results) {
   if (rlb_status s = check_lat(lat)) return s;
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: use the batch's autotuner (rlb_batch_autotune)");
   if (trials < 1 || trials > 1000) return fail(RLB_EINVAL, "trials must be in [1, 1000]");
   const int force = force_mode(lat);
   const LaunchShape best = lat->shape;

@@ -156,6 +156,22 @@ def test_open_channel_batch_equals_single_runs(graph):
         assert torch.equal(B[b].save_state().cpu(), want[b]), b
 
 
+def test_member_rejects_settings_the_batch_holds():
+    need_gpu()
+    from paper_2205_04658_amd.rlb import EINVAL, RLBError
+    B = make_batch()
+    m = B[1]
+    calls = [lambda: m.step(1), lambda: m.set_body_force(1e-4), lambda: m.set_stirring(1, 3, 1e-4, 1),
+             lambda: m.set_relaxation_time(0.7), lambda: m.set_relaxation_eta_s(0.05, 0.05),
+             lambda: m.set_launch_shape(2, 0, 16), lambda: m.autotune(1), lambda: m.use_graph(8),
+             lambda: m.timing(True), lambda: m.record_current(2, 3)]
+    for c in calls:
+        with pytest.raises(RLBError) as e:
+            c()
+        assert e.value.status == EINVAL
+    assert m.step_count == 0
+
+
 def test_autotune_does_not_advance_and_keeps_results():
     torch = need_gpu()
     B = make_batch()
