@@ -303,8 +303,8 @@ def run_part2(torch, rlb, workloads, steps=2000, warmup=100, graph_steps=100):
 
 
 def run_analysis(torch, rlb, workloads, reps=5):
-    """The Part I analysis on forced lattices: one E(k) + filtered-speed
-    evaluation (velocity read-out, float64 2D transform, shells, inverse
+    """The Part I analysis on forced lattices: one E(k) + filtered-speed +
+    enstrophy evaluation (velocity read-out, float64 2D transform, shells, inverse
     transform of the low-pass field) at 1024^2 (shell 7-9) and 4096^2
     (shell 31-33), k_cut = 6, averaged over `reps` calls after a warm one."""
     out = {}
@@ -323,7 +323,7 @@ def run_analysis(torch, rlb, workloads, reps=5):
         e.record(lat.stream)
         e.synchronize()
         out[f"{n}x{n}"] = dict(ms=s.elapsed_time(e) / reps, E_peak_shell=int(E[1:].argmax()) + 1,
-                               filtered_rms=float(sp[0]))
+                               filtered_rms=float(sp[0]), enstrophy=float(sp[2]))
         del lat
         torch.cuda.empty_cache()
     return out

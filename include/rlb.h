@@ -281,6 +281,10 @@ rlb_status rlb_power_spectrum(const double* d_series, int64_t n, double* d_out, 
  *              s = 0 .. kmax (numpy.fft conventions, integer wave numbers);
  *   d_out[kmax+1] = rms |beta_f|, d_out[kmax+2] = mean |beta_f|, beta_f the
  *              velocity keeping only the modes with |k| < k_cut;
+ *   d_out[kmax+3] = enstrophy Z = sum over nodes of omega^2, omega =
+ *              d_x beta_y - d_y beta_x by periodic central differences
+ *              (Ch. 2 "Turbulence"; solid nodes read as beta = 0);
+ * (d_out holds kmax + 4 doubles)
  * and, if d_acc is not null, adds E(s) to d_acc[s] and E(s)^2 to
  * d_acc[kmax+1+s] (running sums for time averages).  d_work: a 256-byte
  * aligned device buffer of rlb_spectrum_workspace_bytes.  Deterministic. */

@@ -170,6 +170,28 @@ __global__ __launch_bounds__(256) void speed_final_kernel(const double* __restri
   if (threadIdx.x == 0) *out = a * inv_n;
 }
 
+// Enstrophy Z = sum over nodes of omega^2, omega = d_x beta_y - d_y beta_x
+// by periodic central differences of the read-out fields (Ch. 2
+// "Turbulence"), float64, per-block partials in a fixed grid.
+__global__ __launch_bounds__(256) void enstrophy_kernel(const float* __restrict__ bx,
+                                                        const float* __restrict__ by, int nx,
+                                                        int ny, double* part) {
+  __shared__ double red[4];
+  double a = 0.0;
+  const int64_t n = (int64_t)nx * ny;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / nx), x = (int)(i - (int64_t)y * nx);
+    const int xp = x + 1 < nx ? x + 1 : 0, xm = x > 0 ? x - 1 : nx - 1;
+    const int yp = y + 1 < ny ? y + 1 : 0, ym = y > 0 ? y - 1 : ny - 1;
+    const double w = 0.5 * ((double)by[(int64_t)y * nx + xp] - (double)by[(int64_t)y * nx + xm]) -
+                     0.5 * ((double)bx[(int64_t)yp * nx + x] - (double)bx[(int64_t)ym * nx + x]);
+    a += w * w;
+  }
+  a = block_sum256(a, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
 // ---------------------------------------------------------------------------
 constexpr int kSpeedBlocks = 1024;
 
@@ -208,6 +230,9 @@ hipError_t launch_spectrum(rlb_lattice* lat, int kmax, double kcut, double* out,
   const uint32_t mask = (1u << RLB_FIELD_BETA_X) | (1u << RLB_FIELD_BETA_Y);
   hipError_t e = launch_step(lat, MODE_FIELDS, FORCE_NONE, lat->cur, f, mask);
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(enstrophy_kernel, dim3(kSpeedBlocks), dim3(256), 0, s, f, f + nodes, nx, ny, sp);
+  hipLaunchKernelGGL(speed_final_kernel, dim3(1), dim3(256), 0, s, sp, kSpeedBlocks, 1.0,
+                     out + kmax + 3);
   const unsigned gn = (unsigned)((nodes + 255) / 256);
   hipLaunchKernelGGL(pack_kernel, dim3(gn), dim3(256), 0, s, f, f + nodes, z, nodes);
   hipLaunchKernelGGL(twiddle64_kernel, dim3((nx / 2 + 255) / 256), dim3(256), 0, s, twx, nx);

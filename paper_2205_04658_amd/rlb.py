@@ -440,15 +440,16 @@ class Lattice:
 
     def energy_spectrum(self, kmax=None, k_cut=0.0, acc=None):
         """E(k) of the current velocity (rlb_energy_spectrum): returns
-        (E tensor [kmax+1], rms and mean speed of the field filtered to
-        |k| < k_cut as a 2-element tensor), all float64 on the device;
-        acc (a float64 tensor [2 (kmax+1)]) collects running sums."""
+        (E tensor [kmax+1], a 3-element tensor: rms and mean speed of the
+        field filtered to |k| < k_cut, and the enstrophy), all float64 on
+        the device; acc (a float64 tensor [2 (kmax+1)]) collects running
+        sums."""
         torch = _torch()
         kmax = min(self.nx, self.ny) // 2 if kmax is None else int(kmax)
         n = _sz()
         check(lib().rlb_spectrum_workspace_bytes(self._h, kmax, ctypes.byref(n)))
         work = torch.empty(n.value, dtype=torch.uint8, device=self.device)
-        out = torch.empty(kmax + 3, dtype=torch.float64, device=self.device)
+        out = torch.empty(kmax + 4, dtype=torch.float64, device=self.device)
         if acc is not None and (acc.dtype != torch.float64 or acc.numel() != 2 * (kmax + 1)):
             raise ValueError("acc must be a float64 tensor of 2 (kmax + 1) elements")
         self._in(out, work, *([acc] if acc is not None else []))

@@ -1,8 +1,9 @@
 """Spectral analysis on the GPU (float64 transforms of the velocity read-out)
-against the oracle: E(k), the filtered speeds and the running sums, on the
-GPU's own fields (only the summation order differs) and on the oracle's
-(field tolerance), square and non-square, with obstacles, and the
-statistics of a 256^2 forced run."""
+against the oracle: E(k), the filtered speeds, the enstrophy and the running
+sums, on the GPU's own fields (only the summation order differs) and on the
+oracle's (field tolerance), square and non-square, with obstacles, and the
+statistics of a 256^2 forced run (the 4096^2 workload's shell, amplitude
+and tau)."""
 import numpy as np
 import pytest
 
@@ -40,6 +41,8 @@ def test_spectrum_of_gpu_fields(nx, ny):
     _, _, mean, rms = diagnostics.filtered_velocity(bx, by, kcut)
     sp = sp.cpu().numpy()
     assert abs(sp[0] - rms) < 1e-12 * rms and abs(sp[1] - mean) < 1e-12 * mean
+    Z = diagnostics.enstrophy(bx, by)
+    assert abs(sp[2] - Z) < 1e-12 * Z
 
 
 def test_running_sums_and_average():
@@ -61,8 +64,8 @@ def test_running_sums_and_average():
 
 def test_spectrum_matches_oracle_run():
     """256 x 256 forced crop (the 4096^2 workload's shell, amplitude and tau
-    on a 256^2 lattice), 30 steps: E(k) and the filtered speeds of the GPU
-    run against those of the oracle run."""
+    on a 256^2 lattice), 30 steps: E(k) and the enstrophy of the GPU run
+    against those of the oracle run."""
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import Lattice
     c = workloads.FORCED_4096
@@ -81,6 +84,8 @@ def test_spectrum_matches_oracle_run():
     band = slice(int(c["kmin"]), int(c["kmax"]) + 1)
     assert np.abs(E[band] - want[band]).max() < 1e-4 * want[band].max()
     assert np.abs(E - want).max() < 1e-4 * want.max()
+    Z = diagnostics.enstrophy(o["beta_x"], o["beta_y"])
+    assert abs(sp[2].item() - Z) < 1e-4 * Z
 
 
 def test_spectrum_rejects_unsupported_sizes():
