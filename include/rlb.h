@@ -461,7 +461,9 @@ rlb_status rlb_set_relaxation_time(rlb_lattice* lat, double tau);
 rlb_status rlb_set_relaxation_eta_s(rlb_lattice* lat, double eta_over_s, double dt);
 
 /* Bytes of the adjoint workspace: ceil(N/K) checkpoints + K segment states
- * + 2 adjoint states + float64 per-node accumulators. */
+ * (twice when there is more than one segment: the next segment is
+ * recomputed while the adjoint sweeps the current one) + 2 adjoint states
+ * + float64 per-node accumulators. */
 rlb_status rlb_adjoint_workspace_bytes(const rlb_lattice* lat, const rlb_adjoint_cfg* cfg,
                                        size_t* bytes);
 
@@ -469,7 +471,10 @@ rlb_status rlb_adjoint_workspace_bytes(const rlb_lattice* lat, const rlb_adjoint
  * (overwriting the lattice's stirring-force planes), write J to
  * *h_objective and, if h_grad is not null, the gradient (2 + M doubles:
  * dJ/dF_b, dJ/dtau, dJ/dA_m) computed by the adjoint.  The lattice is left
- * at step N.  Synchronises.  d_ws: 256-byte aligned device memory. */
+ * at step N.  Synchronises.  d_ws: 256-byte aligned device memory.  The
+ * backward pass also uses a second stream of the library's (created on
+ * first use, default priority, ordered after the lattice stream's prior
+ * work and joined back into it before return). */
 rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d_ws,
                            size_t bytes, double* h_objective, double* h_grad);
 

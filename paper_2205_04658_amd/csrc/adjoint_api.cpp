@@ -2,6 +2,12 @@
 // reverse order -- restore the checkpoint, recompute and store the K states
 // of the segment, sweep the adjoint kernel back through them -- and reduce
 // the per-node parameter adjoints to dJ/d(F_b, tau, A_1..A_M).
+//
+// The recomputed states are double-buffered: segment s - 1 is recomputed on
+// the lattice stream while the adjoint sweeps segment s on a second stream
+// (both are latency-bound on channel-sized lattices).  Events order the
+// buffer reuse; the adjoint kernels keep one stream and one order, so the
+// gradient is the same bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,7 +46,7 @@ rlb_status afail(rlb_status s, const char* fmt, ...) {
 struct AdjLayout {
   size_t state_bytes, ck_off, store_off, mu_off, accf_off, acct_off, obj_off, modes_off,
       partial_off, result_off, desc_off, total;
-  int64_t nseg;
+  int64_t nseg, nbuf;
 };
 
 rlb_status check_cfg(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
@@ -78,7 +84,8 @@ AdjLayout adj_layout(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
   const int64_t K = std::min<int64_t>(c->checkpoint, c->nsteps);
   size_t off = 0;
   L.ck_off = off; off += L.state_bytes * (size_t)L.nseg;
-  L.store_off = off; off += L.state_bytes * (size_t)K;
+  L.nbuf = L.nseg > 1 ? 2 : 1;   // recompute buffers
+  L.store_off = off; off += L.state_bytes * (size_t)K * (size_t)L.nbuf;
   L.mu_off = off; off += 2 * L.state_bytes;
   L.accf_off = off; off += align_up(ncell * sizeof(double2));
   L.acct_off = off; off += align_up(ncell * sizeof(double));
@@ -86,7 +93,7 @@ AdjLayout adj_layout(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
   L.modes_off = off; off += align_up(kMaxModesAdj * 6 * sizeof(double));
   L.partial_off = off; off += align_up((size_t)(2 + kMaxModesAdj) * kGradCols * sizeof(double));
   L.result_off = off; off += align_up(128 * sizeof(double));
-  L.desc_off = off; off += align_up(sizeof(LatDesc) * (size_t)K);
+  L.desc_off = off; off += align_up(sizeof(LatDesc) * (size_t)K * (size_t)L.nbuf);
   L.total = off;
   return L;
 }
@@ -138,7 +145,7 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
   const size_t SB = L.state_bytes;
   const size_t state_copy = (size_t)2 * lat->Q * lat->pitch * sizeof(float);
   auto ck = [&](int64_t k) { return (float*)(ws + L.ck_off + SB * k); };
-  auto store = [&](int64_t j) { return (float*)(ws + L.store_off + SB * j); };
+  auto store = [&](int64_t b, int64_t j) { return (float*)(ws + L.store_off + SB * (b * K + j)); };
   float* mu[2] = {(float*)(ws + L.mu_off), (float*)(ws + L.mu_off + SB)};
   double2* acc_f = (double2*)(ws + L.accf_off);
   double* acc_t = (double*)(ws + L.acct_off);
@@ -165,15 +172,17 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
   StepShared sh = shared_of(lat);
   const bool unit = lat->p.cfl == 1.0, mask = lat->any_solid;
 
-  // recompute descriptors: store[j] -> store[j + 1]
-  std::vector<LatDesc> hd((size_t)K);
-  for (int64_t j = 0; j < K; ++j) {
-    LatDesc d = lat->desc;
-    d.state[0] = store(j);
-    d.state[1] = store(std::min<int64_t>(j + 1, K - 1));
-    hd[j] = d;
-  }
-  AHIP(hipMemcpyAsync(d_desc, hd.data(), sizeof(LatDesc) * K, hipMemcpyHostToDevice, st), "descriptors");
+  // recompute descriptors of buffer b: store(b, j) -> store(b, j + 1)
+  std::vector<LatDesc> hd((size_t)(K * L.nbuf));
+  for (int64_t b = 0; b < L.nbuf; ++b)
+    for (int64_t j = 0; j < K; ++j) {
+      LatDesc d = lat->desc;
+      d.state[0] = store(b, j);
+      d.state[1] = store(b, std::min<int64_t>(j + 1, K - 1));
+      hd[(size_t)(b * K + j)] = d;
+    }
+  AHIP(hipMemcpyAsync(d_desc, hd.data(), sizeof(LatDesc) * hd.size(), hipMemcpyHostToDevice, st),
+       "descriptors");
   AHIP(hipStreamSynchronize(st), "stream synchronize");
 
   ObjArgs oa;
@@ -223,9 +232,18 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
 
   if (h_grad) {
     // ---- backward ----
+    if (!lat->aux) {
+      AHIP(hipStreamCreateWithFlags(&lat->aux, hipStreamNonBlocking), "second stream");
+      for (auto& e : lat->aux_ev) AHIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    }
+    hipStream_t sa = lat->aux;   // the adjoint sweep
+    hipEvent_t ev_fwd = lat->aux_ev[0], ev_rec = lat->aux_ev[1], ev_join = lat->aux_ev[2];
+    hipEvent_t ev_adj[2] = {lat->aux_ev[3], lat->aux_ev[4]};
     const size_t ncell = (size_t)nx * ny;
     AHIP(launch_zero_f64((double*)acc_f, 2 * ncell, st), "zero");
     AHIP(launch_zero_f64(acc_t, ncell, st), "zero");
+    AHIP(hipEventRecord(ev_fwd, st), "event record");
+    AHIP(hipStreamWaitEvent(sa, ev_fwd, 0), "stream wait");
     AdjArgs aa;
     aa.sh = sh;
     aa.mask = mask ? lat->mask : nullptr;
@@ -245,7 +263,7 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
     aa.mu_in = nullptr;
     aa.mu_out = mu[cm];
     aa.obj_c = (float)cw;
-    AHIP(launch_adjoint(lat->Q, unit, mask, aa, st), "adjoint");
+    AHIP(launch_adjoint(lat->Q, unit, mask, aa, sa), "adjoint");
     TileArgs ta;
     ta.sh = sh;
     ta.tile_lat = nullptr;
@@ -253,23 +271,41 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
     ta.tile_first = 0;
     ta.ntiles = tiles_of(nx, ny, lat->Q == 17 ? lat->shape.tile_rows : 4);
     ta.fields = nullptr;
-    for (int64_t seg = L.nseg - 1; seg >= 0; --seg) {
-      const int64_t t0 = seg * K, len = std::min<int64_t>(K, N - t0);
-      AHIP(hipMemcpyAsync(store(0), ck(seg), state_copy, hipMemcpyDeviceToDevice, st), "restore");
+    // restore segment seg's checkpoint into buffer seg % nbuf and recompute
+    // its states on the lattice stream
+    auto recompute = [&](int64_t seg) -> rlb_status {
+      const int64_t b = seg % L.nbuf, len = std::min<int64_t>(K, N - seg * K);
+      AHIP(hipMemcpyAsync(store(b, 0), ck(seg), state_copy, hipMemcpyDeviceToDevice, st), "restore");
       for (int64_t j = 0; j + 1 < len; ++j) {
-        ta.lats = d_desc + j;
-        AHIP(launch_tiles(lat->Q, stream_mode(lat->p.cfl), mask, MODE_STEP, FORCE_STIR, ta, lat->shape, lat->num_cu, st),
-             "recompute");
+        ta.lats = d_desc + b * K + j;
+        AHIP(launch_tiles(lat->Q, stream_mode(lat->p.cfl), mask, MODE_STEP, FORCE_STIR, ta, lat->shape,
+                          lat->num_cu, st), "recompute");
       }
+      AHIP(hipEventRecord(ev_rec, st), "event record");
+      return RLB_OK;
+    };
+    if (rlb_status s = recompute(L.nseg - 1)) return s;
+    for (int64_t seg = L.nseg - 1; seg >= 0; --seg) {
+      const int64_t t0 = seg * K, len = std::min<int64_t>(K, N - t0), b = seg % L.nbuf;
+      AHIP(hipStreamWaitEvent(sa, ev_rec, 0), "stream wait");   // segment seg recomputed
       for (int64_t t = t0 + len - 1; t >= t0; --t) {
-        aa.state = store(t - t0);
+        aa.state = store(b, t - t0);
         aa.mu_in = mu[cm];
         aa.mu_out = mu[cm ^ 1];
         aa.obj_c = t > N / 2 ? (float)cw : 0.0f;
-        AHIP(launch_adjoint(lat->Q, unit, mask, aa, st), "adjoint");
+        AHIP(launch_adjoint(lat->Q, unit, mask, aa, sa), "adjoint");
         cm ^= 1;
       }
+      AHIP(hipEventRecord(ev_adj[seg & 1], sa), "event record");
+      if (seg > 0) {
+        // the buffer of segment seg - 1 was last read by the sweep of seg + 1
+        // (nbuf is 2 whenever there is more than one segment)
+        if (seg + 1 < L.nseg) AHIP(hipStreamWaitEvent(st, ev_adj[(seg + 1) & 1], 0), "stream wait");
+        if (rlb_status s = recompute(seg - 1)) return s;
+      }
     }
+    AHIP(hipEventRecord(ev_join, sa), "event record");
+    AHIP(hipStreamWaitEvent(st, ev_join, 0), "stream wait");
     AHIP(launch_grad_reduce(acc_f, acc_t, d_modes, M, nx, ny, lat->p.tau, partial, kGradCols,
                             result + 1, st), "gradient reduce");
     std::vector<double> g((size_t)(2 + M));

@@ -323,6 +323,12 @@ static void drop_lattice_graph(rlb_lattice* lat) {
 rlb_status rlb_destroy(rlb_lattice* lat) {
   if (!lat) return RLB_OK;
   drop_lattice_graph(lat);
+  if (lat->aux) {
+    (void)hipStreamSynchronize(lat->aux);
+    (void)hipStreamDestroy(lat->aux);
+    for (auto& e : lat->aux_ev)
+      if (e) (void)hipEventDestroy(e);
+  }
   if (lat->ev[0][0]) {
     for (int i = 0; i < kEvRing; ++i)
       for (int j = 0; j < 2; ++j)

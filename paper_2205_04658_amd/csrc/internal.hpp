@@ -202,6 +202,10 @@ struct rlb_lattice {
   hipGraph_t graph;
   hipGraphExec_t exec;
   double graph_key[24];
+  // second stream and events of the adjoint's backward pass (created on
+  // first use)
+  hipStream_t aux;
+  hipEvent_t aux_ev[5];
   // saved-state header staging
   alignas(64) unsigned char header[256];
 };
