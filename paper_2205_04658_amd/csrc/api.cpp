@@ -85,10 +85,13 @@ Workspace layout(const rlb_params* p, int Q, int64_t pitch) {
   w.coef_off = off; off += align_up((size_t)kMaxModes * 4 * sizeof(double));
   w.modes_off = off; off += align_up((size_t)kMaxModes * sizeof(int4));
   w.bins_off = off; off += align_up((size_t)(kMaxK + 2) * sizeof(int32_t));
-  w.table_off = off; off += align_up((size_t)p->ny * (kMaxK + 1) * sizeof(float4));
+  // series coefficients: (kMaxK + 1) / 8 chunks x 2 halves x ny rows x
+  // 2 components x hi | lo, 16 bytes each
+  w.table_off = off; off += align_up((size_t)(kMaxK + 1) / 8 * 2 * p->ny * 4 * sizeof(uint4));
   w.phase_off = off; off += align_up((size_t)p->ny * sizeof(double2));
   w.force_off = off; off += align_up((size_t)2 * pitch * sizeof(float));
-  w.twiddle_off = off; off += align_up((size_t)(kMaxK + 1) * p->nx * sizeof(float2));
+  // twiddles: (kMaxK + 1) / 8 chunks x 2 halves x nx columns x hi | lo
+  w.twiddle_off = off; off += align_up((size_t)(kMaxK + 1) / 8 * 2 * p->nx * 2 * sizeof(uint4));
   w.partial_off = off; off += align_up((size_t)kRedBlocks * 4 * sizeof(double));
   w.desc_off = off; off += align_up(sizeof(LatDesc));
   w.misc_off = off; off += align_up(256);
@@ -140,6 +143,8 @@ StirArgs stir_args(const rlb_lattice* lat) {
   a.table = lat->table;
   a.phase = lat->phase;
   a.twiddle = lat->twiddle;
+  a.scale = lat->stir_scale > 0.0f ? lat->stir_scale : 1.0f;   // 0 before rlb_set_stirring
+  a.inv_scale = 1.0f / a.scale;
   a.force = lat->force;
   a.force_pitch = lat->pitch;
   a.row = lat->row;
@@ -260,10 +265,10 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   lat->coef = (double*)(lat->ws + w.coef_off);
   lat->modes = (int4*)(lat->ws + w.modes_off);
   lat->bins = (int32_t*)(lat->ws + w.bins_off);
-  lat->table = (float4*)(lat->ws + w.table_off);
+  lat->table = (uint4*)(lat->ws + w.table_off);
   lat->phase = (double2*)(lat->ws + w.phase_off);
   lat->force = (float*)(lat->ws + w.force_off);
-  lat->twiddle = (float2*)(lat->ws + w.twiddle_off);
+  lat->twiddle = (uint4*)(lat->ws + w.twiddle_off);
   lat->partials = (double*)(lat->ws + w.partial_off);
   lat->err = (uint32_t*)(lat->ws + w.misc_off);
   lat->dstep = (int64_t*)(lat->ws + w.misc_off + 64);
@@ -456,6 +461,14 @@ rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax, double a
   lat->seed = seed;
   lat->nmodes = (int)modes.size();
   lat->K = kmaxx;
+  // the series coefficients are about 2 amplitude sqrt(modes of a bin) or
+  // less: a power of two brings that to ~2^8, well inside float16's normal
+  // range, before the hi + lo split
+  {
+    const double typ = 2.0 * amplitude * std::sqrt((double)modes.size());
+    const int e = std::max(-60, std::min(60, 8 - (int)std::ceil(std::log2(typ))));
+    lat->stir_scale = std::ldexp(1.0f, e);
+  }
   HIP_TRY(launch_twiddle(lat->twiddle, kmaxx, lat->p.nx, lat->stream), "twiddle table");
   HIP_TRY(launch_set_i64(lat->dstep, lat->step, lat->stream), "step counter");
   return RLB_OK;

@@ -10,8 +10,12 @@
 // order; (3) the synthesis kernel evaluates the series at every node and
 // writes the two force planes the step kernel reads.  The synthesis is a
 // dense product, F_c(y, x) = sum_j A_c(y, j) T(j, x) over the 2 (K + 1)
-// slots j = (k, cos | sin), so it runs on the matrix cores: float32
-// v_mfma_f32_32x32x2f32, one k (two slots) per instruction.
+// slots j = (k, cos | sin), so it runs on the matrix cores.  Both operands
+// are split into float16 hi + lo parts (the coefficients scaled by a power
+// of two into float16's normal range), and hi*hi + hi*lo + lo*hi is
+// accumulated in float32 by v_mfma_f32_32x32x16_f16, eight k (16 slots) per
+// instruction: 22 significant bits per operand, about float32's accuracy,
+// at a fifth of the float32 matrix instructions' cycles.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -41,15 +45,25 @@ __global__ __launch_bounds__(256) void stir_draw_kernel(const StirArgs a,
   if (fixed_step < 0 && threadIdx.x == 0) *a.dstep = t + 1;
 }
 
-// Series coefficients: the table holds, for every |kx| = k and row y,
-// (a_k, b_k) of F^x and F^y as one float4 at [k][y] (k-major, so the
-// synthesis reads 32 consecutive rows per load).  One wavefront covers 64
-// rows of one k and sums the modes of that bin in their fixed order: mode
-// (kx, ky) with coefficient c contributes prod = 2 c e^{2 pi i ky y / ny}
-// to cos(k th) with Re(prod) and to sin(k th) with -sign(kx) Im(prod).
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// float16 hi + lo split of v: hi = v rounded, lo = the rest rounded, so
+// hi + lo = v to about 2^-22 relative while |v| is a normal float16.
+__device__ __forceinline__ void split16(double v, _Float16& hi, _Float16& lo) {
+  hi = (_Float16)v;
+  lo = (_Float16)(v - (double)hi);
+}
+
+// Series coefficients: (a_k, b_k) of F^x and F^y for every |kx| = k and row
+// y, times the lattice's power-of-two scale, in the synthesis's operand
+// order (see StirArgs::table).  One thread per (k, y) sums the modes of its
+// bin in their fixed order: mode (kx, ky) with coefficient c contributes
+// prod = 2 c e^{2 pi i ky y / ny} to cos(k th) with Re(prod) and to
+// sin(k th) with -sign(kx) Im(prod).  Rows k past K are written as zeros.
 __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a) {
   const int y = blockIdx.x * 64 + threadIdx.x;
-  const int k = blockIdx.y;   // 0 .. K rounded up to 4 (rows past K are zero)
+  const int k = blockIdx.y;   // 0 .. 8 chunks(K) - 1
   if (y >= a.ny) return;
   double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
   const int j1 = k <= a.K ? a.bins[k + 1] : 0;
@@ -69,47 +83,59 @@ __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a) {
     ay += pyr;
     by += sg * pyi;
   }
-  a.table[(size_t)k * a.ny + y] =
-      make_float4((float)ax, (float)(k ? bx : 0.0), (float)ay, (float)(k ? by : 0.0));
+  if (k == 0) bx = by = 0.0;
+  const double sc = (double)a.scale;
+  const double v[2][2] = {{ax * sc, bx * sc}, {ay * sc, by * sc}};
+  // item (k / 8, (k / 4) % 2, y, component, hi | lo); halves 2 (k % 4), +1
+  _Float16* base = (_Float16*)(a.table + ((size_t)((k >> 3) * 2 + ((k >> 2) & 1)) * a.ny + y) * 4);
+  const int p = 2 * (k & 3);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    _Float16 h0, l0, h1, l1;
+    split16(v[c][0], h0, l0);
+    split16(v[c][1], h1, l1);
+    _Float16* hi = base + 8 * (2 * c);
+    _Float16* lo = base + 8 * (2 * c + 1);
+    hi[p] = h0; hi[p + 1] = h1;
+    lo[p] = l0; lo[p + 1] = l1;
+  }
 }
 
-// Column twiddles (cos, sin)(2 pi k x / nx) for k = 0..kMaxK, table
-// [kMaxK + 1][nx], exactly reduced; rows past K are zero (the synthesis
-// runs k up to a multiple of 4).  Static per lattice and shell.
-__global__ __launch_bounds__(256) void twiddle_kernel(float2* tw, int K, int nx) {
+// Column twiddles (cos, sin)(2 pi k x / nx) for k = 0..kMaxK as float16
+// hi + lo in the synthesis's operand order (see StirArgs::twiddle), exactly
+// reduced; rows past K are zero.  Static per lattice and shell.
+__global__ __launch_bounds__(256) void twiddle_kernel(uint4* tw, int K, int nx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (kMaxK + 1) * nx) return;
   const int k = i / nx, x = i - k * nx;
-  float2 v = make_float2(0.0f, 0.0f);
-  if (k <= K) {
-    double sn, cs;
-    sincospi(2.0 * (double)(((long long)k * x) % nx) / (double)nx, &sn, &cs);
-    v = make_float2((float)cs, (float)sn);
-  }
-  tw[i] = v;
+  double sn = 0.0, cs = 0.0;
+  if (k <= K) sincospi(2.0 * (double)(((long long)k * x) % nx) / (double)nx, &sn, &cs);
+  _Float16* base = (_Float16*)(tw + ((size_t)((k >> 3) * 2 + ((k >> 2) & 1)) * nx + x) * 2);
+  const int p = 2 * (k & 3);
+  _Float16 hc, lc, hs, ls;
+  split16(cs, hc, lc);
+  split16(sn, hs, ls);
+  base[p] = hc; base[p + 1] = hs;
+  base[8 + p] = lc; base[8 + p + 1] = ls;
 }
-
-typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kSynthBlocks = 4;                  // 32-column blocks per wavefront
 constexpr int kSynthWaveCols = 32 * kSynthBlocks;
 constexpr int kSynthWaves = 4;                   // wavefronts per workgroup
 
-// Number of k the synthesis runs: K + 1 rounded up to a multiple of 4 (<= 64).
-static inline int synth_slots(int K) { return (K + 4) & ~3; }
+// Chunks of eight k the synthesis runs: ceil((K + 1) / 8) (<= 8).
+static inline int synth_chunks(int K) { return (K + 8) >> 3; }
 
 // One wavefront: rows y0 .. y0+31, columns xw .. xw+127, both components.
-// For each k the A operand holds the rows' (a_k, b_k) -- lanes 0-31 the cos
-// coefficient of row y0 + lane, lanes 32-63 the sin coefficient -- and the
-// B operand the columns' (cos, sin)(k th) in the same split, so one 32x32x2
-// product adds a_k cos(k th) + b_k sin(k th) to a 32 x 32 block.
-// Accumulator element i of lane l is block row 8 (i / 4) + 4 (l / 32) +
-// i % 4, column l % 32.  Both tables are zero past K, so the k loop is
-// loads and products only.  Rows and columns past the lattice are clamped
-// on load and skipped on store.
+// v_mfma_f32_32x32x16_f16 takes, in lane l, A row l % 32 and B column l % 32
+// with slots 8 (l / 32) .. +7, i.e. (cos, sin) of k = 8 c + 4 (l / 32) .. +3
+// for chunk c: exactly one 16-byte table item each.  Accumulator element i
+// of lane l is block row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
+// Rows and columns past the lattice are clamped on load and skipped on
+// store.
 __global__ __launch_bounds__(64 * kSynthWaves) void stir_synth_kernel(
-    const float4* __restrict__ table, const float2* __restrict__ tw, float* __restrict__ force,
-    int64_t force_pitch, int kslots, int nx, int ny, int row_pitch) {
+    const uint4* __restrict__ table, const uint4* __restrict__ tw, float* __restrict__ force,
+    int64_t force_pitch, int nchunks, int nx, int ny, int row_pitch, float inv_scale) {
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5, l32 = lane & 31;
   const int tiles_x = (nx + kSynthWaveCols - 1) / kSynthWaveCols;
@@ -118,38 +144,36 @@ __global__ __launch_bounds__(64 * kSynthWaves) void stir_synth_kernel(
   const int y0 = ty * 32;
   const int xw = (tile - ty * tiles_x) * kSynthWaveCols;
   if (y0 >= ny) return;   // wave-uniform
-  // Each lane loads only its half: component `half` of every coefficient
-  // pair and of every float2 twiddle (cos or sin), as a wave-uniform base
-  // (the k row) plus a per-lane 32-bit offset (row or column).
-  const uint32_t ao = 16u * (uint32_t)min(y0 + l32, ny - 1) + 4u * half;
-  uint32_t bo[kSynthBlocks];
+  const int ya = min(y0 + l32, ny - 1);
+  int xb[kSynthBlocks];
 #pragma unroll
-  for (int b = 0; b < kSynthBlocks; ++b)
-    bo[b] = 8u * (uint32_t)min(xw + 32 * b + l32, nx - 1) + 4u * half;
+  for (int b = 0; b < kSynthBlocks; ++b) xb[b] = min(xw + 32 * b + l32, nx - 1);
   floatx16 acc[2][kSynthBlocks];
 #pragma unroll
   for (int b = 0; b < kSynthBlocks; ++b) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) { acc[0][b][i] = 0.0f; acc[1][b][i] = 0.0f; }
   }
-  for (int k0 = 0; k0 < kslots; k0 += 4) {
-    float ax[4], ay[4], bv[4][kSynthBlocks];
+  for (int c = 0; c < nchunks; ++c) {
+    const size_t part = (size_t)(2 * c + half);
+    const uint4* ap = table + (part * ny + ya) * 4;
+    const half8 axh = __builtin_bit_cast(half8, ap[0]), axl = __builtin_bit_cast(half8, ap[1]);
+    const half8 ayh = __builtin_bit_cast(half8, ap[2]), ayl = __builtin_bit_cast(half8, ap[3]);
+    half8 bh[kSynthBlocks], bl[kSynthBlocks];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const gbyte* ak = (const gbyte*)(table + (size_t)(k0 + j) * ny);
-      ax[j] = *(const gfloat*)(ak + ao);
-      ay[j] = *(const gfloat*)(ak + ao + 8);
-      const gbyte* tk = (const gbyte*)(tw + (size_t)(k0 + j) * nx);
-#pragma unroll
-      for (int b = 0; b < kSynthBlocks; ++b) bv[j][b] = *(const gfloat*)(tk + bo[b]);
+    for (int b = 0; b < kSynthBlocks; ++b) {
+      const uint4* bp = tw + (part * nx + xb[b]) * 2;
+      bh[b] = __builtin_bit_cast(half8, bp[0]);
+      bl[b] = __builtin_bit_cast(half8, bp[1]);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-#pragma unroll
-      for (int b = 0; b < kSynthBlocks; ++b) {
-        acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ax[j], bv[j][b], acc[0][b], 0, 0, 0);
-        acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ay[j], bv[j][b], acc[1][b], 0, 0, 0);
-      }
+    for (int b = 0; b < kSynthBlocks; ++b) {
+      acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(axl, bh[b], acc[0][b], 0, 0, 0);
+      acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(axh, bl[b], acc[0][b], 0, 0, 0);
+      acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(axh, bh[b], acc[0][b], 0, 0, 0);
+      acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ayl, bh[b], acc[1][b], 0, 0, 0);
+      acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ayh, bl[b], acc[1][b], 0, 0, 0);
+      acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ayh, bh[b], acc[1][b], 0, 0, 0);
     }
   }
   // store block by block (the barriers keep one block's accumulators in
@@ -161,8 +185,8 @@ __global__ __launch_bounds__(64 * kSynthWaves) void stir_synth_kernel(
     for (int i = 0; i < 16; ++i) {
       const int y = y0 + 8 * (i >> 2) + 4 * half + (i & 3);
       if (x < nx && y < ny) {
-        force[(size_t)y * row_pitch + x] = acc[0][b][i];
-        force[force_pitch + (size_t)y * row_pitch + x] = acc[1][b][i];
+        force[(size_t)y * row_pitch + x] = acc[0][b][i] * inv_scale;
+        force[force_pitch + (size_t)y * row_pitch + x] = acc[1][b][i] * inv_scale;
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -200,7 +224,7 @@ hipError_t launch_stir_draw(const StirArgs& a, int64_t fixed_step,
 }
 
 hipError_t launch_stir_table(const StirArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(stir_table_kernel, dim3((a.ny + 63) / 64, synth_slots(a.K)), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(stir_table_kernel, dim3((a.ny + 63) / 64, 8 * synth_chunks(a.K)), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -208,11 +232,11 @@ hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s) {
   const int tiles = ((a.nx + kSynthWaveCols - 1) / kSynthWaveCols) * ((a.ny + 31) / 32);
   hipLaunchKernelGGL(stir_synth_kernel, dim3((tiles + kSynthWaves - 1) / kSynthWaves),
                      dim3(64 * kSynthWaves), 0, s, a.table, a.twiddle, a.force, a.force_pitch,
-                     synth_slots(a.K), a.nx, a.ny, a.row);
+                     synth_chunks(a.K), a.nx, a.ny, a.row, a.inv_scale);
   return hipGetLastError();
 }
 
-hipError_t launch_twiddle(float2* tw, int K, int nx, hipStream_t s) {
+hipError_t launch_twiddle(uint4* tw, int K, int nx, hipStream_t s) {
   hipLaunchKernelGGL(twiddle_kernel, dim3(((kMaxK + 1) * nx + 255) / 256), dim3(256), 0, s, tw, K, nx);
   return hipGetLastError();
 }

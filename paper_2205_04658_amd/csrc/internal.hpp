@@ -89,9 +89,16 @@ struct StirArgs {
   const int4* modes;      // binned list (m, kx, ky, 0), grouped by |kx|
   const int32_t* bins;    // [K+2] offsets of |kx| = 0..K in `modes`
   double* coef;           // [nmodes][4] (Re Fx, Im Fx, Re Fy, Im Fy)
-  float4* table;          // [kMaxK+1][ny] series coefficients (a_k, b_k) of F^x, F^y
+  // series coefficients (a_k, b_k) of F^x, F^y times `scale`, as float16
+  // hi + lo pairs in matrix-operand order: 16-byte items
+  // [k / 8][(k / 4) % 2][ny][component][hi | lo] of 8 halves
+  // (a_k, b_k for 4 consecutive k), zero past K
+  uint4* table;
   const double2* phase;   // [ny] (cos, sin)(2 pi m / ny)
-  const float2* twiddle;  // [kMaxK+1][nx] (cos, sin)(2 pi k x / nx), zero past K
+  // (cos, sin)(2 pi k x / nx) as float16 hi + lo pairs: 16-byte items
+  // [k / 8][(k / 4) % 2][nx][hi | lo] of 8 halves, zero past K
+  const uint4* twiddle;
+  float scale, inv_scale; // power of two keeping the coefficients in float16's normal range
   float* force;           // [2][force_pitch] synthesised force planes, rows padded
   int64_t force_pitch;
   int32_t row;
@@ -169,9 +176,9 @@ struct rlb_lattice {
   double* coef;
   int4* modes;
   int32_t* bins;
-  float4* table;
+  uint4* table;
   double2* phase;
-  float2* twiddle;
+  uint4* twiddle;
   float* force;
   double* partials;
   uint32_t* err;
@@ -183,6 +190,7 @@ struct rlb_lattice {
   rlb::OpenArgs open;     // open x borders (RLB_OPEN_X)
   bool stir;
   double kmin, kmax, amp;
+  float stir_scale;       // power of two applied to the series coefficients
   uint64_t seed;
   int nmodes, K;
   // bilinear tap weights per plane
@@ -262,7 +270,7 @@ hipError_t launch_stir_draw(const StirArgs& a, int64_t fixed_step,
 hipError_t launch_stir_table(const StirArgs& a, hipStream_t s);
 hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s);
 hipError_t launch_phase(const rlb_lattice* lat);
-hipError_t launch_twiddle(float2* tw, int K, int nx, hipStream_t s);
+hipError_t launch_twiddle(uint4* tw, int K, int nx, hipStream_t s);
 hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count,
                          uint64_t* out, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
