@@ -119,14 +119,15 @@ __global__ __launch_bounds__(256) void twiddle_kernel(uint4* tw, int K, int nx) 
   base[8 + p] = lc; base[8 + p + 1] = ls;
 }
 
-constexpr int kSynthBlocks = 4;                  // 32-column blocks per wavefront
+constexpr int kSynthBlocks = 2;                  // 32-column blocks per wavefront
 constexpr int kSynthWaveCols = 32 * kSynthBlocks;
 constexpr int kSynthWaves = 4;                   // wavefronts per workgroup
 
 // Chunks of eight k the synthesis runs: ceil((K + 1) / 8) (<= 8).
 static inline int synth_chunks(int K) { return (K + 8) >> 3; }
 
-// One wavefront: rows y0 .. y0+31, columns xw .. xw+127, both components.
+// One wavefront: rows y0 .. y0+31, columns xw .. xw + 32 kSynthBlocks - 1,
+// both components.
 // v_mfma_f32_32x32x16_f16 takes, in lane l, A row l % 32 and B column l % 32
 // with slots 8 (l / 32) .. +7, i.e. (cos, sin) of k = 8 c + 4 (l / 32) .. +3
 // for chunk c: exactly one 16-byte table item each.  Accumulator element i
