@@ -66,18 +66,30 @@ __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a) {
   const int k = blockIdx.y;   // 0 .. 8 chunks(K) - 1
   if (y >= a.ny) return;
   double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
-  const int j1 = k <= a.K ? a.bins[k + 1] : 0;
-  for (int j = k <= a.K ? a.bins[k] : 0; j < j1; ++j) {
-    const int4 md = a.modes[j];
+  // the bin's modes and their drawn coefficients are the same for every
+  // thread of the workgroup and read-only here (written by earlier
+  // launches): read them through the constant address space, i.e. with
+  // scalar loads
+  typedef const __attribute__((address_space(4))) int CInt;
+  typedef const __attribute__((address_space(4))) double CDouble;
+  CInt* bins = (CInt*)a.bins;
+  CInt* modes = (CInt*)a.modes;
+  CDouble* coef = (CDouble*)a.coef;
+  const int j1 = k <= a.K ? bins[k + 1] : 0;
+  // unrolled so that several phase-table reads are in flight at once
+#pragma unroll 4
+  for (int j = k <= a.K ? bins[k] : 0; j < j1; ++j) {
+    const int md_x = modes[4 * j], md_y = modes[4 * j + 1], md_z = modes[4 * j + 2];
     // e^{2 pi i ky y / ny} from the phase table, index reduced exactly
-    const double2 e = a.phase[((long long)md.z * y) % a.ny];
+    // (0 <= ky <= 63 and y < ny < 2^24: the product fits 32 bits)
+    const double2 e = a.phase[(unsigned)(md_z * y) % (unsigned)a.ny];
     const double cs = e.x, sn = e.y;
-    const double* c = a.coef + 4 * (size_t)md.x;
+    CDouble* c = coef + 4 * (size_t)md_x;
     const double pxr = 2.0 * (c[0] * cs - c[1] * sn);
     const double pxi = 2.0 * (c[0] * sn + c[1] * cs);
     const double pyr = 2.0 * (c[2] * cs - c[3] * sn);
     const double pyi = 2.0 * (c[2] * sn + c[3] * cs);
-    const double sg = md.y > 0 ? -1.0 : 1.0;   // kx = 0 has no sine part
+    const double sg = md_y > 0 ? -1.0 : 1.0;   // kx = 0 has no sine part
     ax += pxr;
     bx += sg * pxi;
     ay += pyr;
