@@ -89,7 +89,10 @@ AdjLayout adj_layout(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
   L.mu_off = off; off += 2 * L.state_bytes;
   L.accf_off = off; off += align_up(ncell * sizeof(double2));
   L.acct_off = off; off += align_up(ncell * sizeof(double));
-  L.obj_off = off; off += align_up(2 * kObjBlocks * sizeof(double));
+  // objective partials: kernel blocks (count, final state), then one slot
+  // per row and 64-node column of the step kernel's wavefronts
+  L.obj_off = off;
+  off += align_up((2 * kObjBlocks + (size_t)lat->p.ny * ((lat->p.nx + 63) / 64)) * sizeof(double));
   L.modes_off = off; off += align_up(kMaxModesAdj * 6 * sizeof(double));
   L.partial_off = off; off += align_up((size_t)(2 + kMaxModesAdj) * kGradCols * sizeof(double));
   L.result_off = off; off += align_up(128 * sizeof(double));
@@ -150,6 +153,8 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
   double2* acc_f = (double2*)(ws + L.accf_off);
   double* acc_t = (double*)(ws + L.acct_off);
   double* obj = (double*)(ws + L.obj_off);
+  const size_t nslots = (size_t)ny * ((nx + 63) / 64);
+  double* obj_slots = obj + 2 * kObjBlocks;   // step-kernel wavefront slots
   double* d_modes = (double*)(ws + L.modes_off);
   double* partial = (double*)(ws + L.partial_off);
   double* result = (double*)(ws + L.result_off);
@@ -192,7 +197,7 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
   oa.nx = nx;
   oa.ny = ny;
   oa.row = lat->row;
-  AHIP(launch_zero_f64(obj, 2 * kObjBlocks, st), "zero objective");
+  AHIP(launch_zero_f64(obj, 2 * kObjBlocks + nslots, st), "zero objective");
   // fluid node count
   oa.state = lat->state[lat->cur];
   oa.acc = obj + kObjBlocks;
@@ -212,23 +217,29 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
   oa.acc = obj;
 
   // ---- forward with checkpoints ----
+  // J_t of the states s_t, N/2 < t < N, is summed by the step kernel that
+  // streams s_t (MODE_OBJ, per-wavefront slots); s_N by the objective kernel
   for (int64_t t = 0; t < N; ++t) {
     if (t % K == 0)
       AHIP(hipMemcpyAsync(ck(t / K), lat->state[lat->cur], state_copy, hipMemcpyDeviceToDevice, st),
            "checkpoint");
-    AHIP(launch_step(lat, MODE_STEP, FORCE_STIR, lat->cur, nullptr, 0), "step");
+    if (t > N / 2)
+      AHIP(launch_step(lat, MODE_OBJ, FORCE_STIR, lat->cur, nullptr, 0, nullptr, 0, obj_slots,
+                       cfg->objective), "step");
+    else
+      AHIP(launch_step(lat, MODE_STEP, FORCE_STIR, lat->cur, nullptr, 0), "step");
     lat->cur ^= 1;
     lat->step += 1;
-    if (t + 1 > N / 2) {
-      oa.state = lat->state[lat->cur];
-      AHIP(launch_objective(lat->Q, unit, mask, oa, kObjBlocks, st), "objective");
-    }
   }
-  AHIP(launch_sum_rows(obj, kObjBlocks, 1, cw, result, st), "objective sum");
-  double J = 0.0;
-  AHIP(hipMemcpyAsync(&J, result, sizeof(double), hipMemcpyDeviceToHost, st), "read objective");
+  oa.state = lat->state[lat->cur];
+  AHIP(launch_objective(lat->Q, unit, mask, oa, kObjBlocks, st), "objective");
+  AHIP(launch_sum_rows(obj, kObjBlocks, 1, 1.0, result, st), "objective sum");
+  AHIP(launch_sum_rows(obj_slots, (int)nslots, 1, 1.0, result + 100, st), "objective sum");
+  double Jp[2] = {0.0, 0.0};
+  AHIP(hipMemcpyAsync(&Jp[0], result, sizeof(double), hipMemcpyDeviceToHost, st), "read objective");
+  AHIP(hipMemcpyAsync(&Jp[1], result + 100, sizeof(double), hipMemcpyDeviceToHost, st), "read objective");
   AHIP(hipStreamSynchronize(st), "stream synchronize");
-  *h_objective = J;
+  *h_objective = cw * (Jp[1] + Jp[0]);
 
   if (h_grad) {
     // ---- backward ----

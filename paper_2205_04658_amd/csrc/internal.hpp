@@ -28,7 +28,9 @@ inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a
 
 // Step-kernel modes: a step, the field read-out, or a step that also sets
 // the open x borders of the new state (velocity inlet, pressure outlet).
-enum StepMode : int { MODE_STEP = 0, MODE_FIELDS = 1, MODE_OPEN = 2 };
+// MODE_OBJ: a step that also adds the adjoint objective's density of the
+// state it streams to per-wavefront slots (StepShared::obj).
+enum StepMode : int { MODE_STEP = 0, MODE_FIELDS = 1, MODE_OPEN = 2, MODE_OBJ = 3 };
 // Force modes: none, uniform body force, body force + k-shell stirring.
 enum ForceMode : int { FORCE_NONE = 0, FORCE_BODY = 1, FORCE_STIR = 2 };
 
@@ -46,6 +48,8 @@ struct StepShared {
   uint32_t field_mask;    // MODE_FIELDS selection
   double* rec;            // non-null (records_current): J^x of the streamed
   int32_t rec_x;          //   populations at column rec_x written to rec[y] (row y)
+  double* obj;            // MODE_OBJ: slot y * tiles_x + x / 64 += the wavefront's
+  int32_t obj_kind;       //   sum of J^x (kind 0) or pi:pi (kind 1) over fluid nodes
 };
 
 // One lattice as the tile kernel sees it (device memory, read with scalar
@@ -239,7 +243,8 @@ int tiles_of(int nx, int ny, int tile_rows);
 std::vector<LaunchShape> launch_candidates(int Q);
 hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode,
                        int parity, float* fields, uint32_t field_mask,
-                       double* rec = nullptr, int rec_x = 0);
+                       double* rec = nullptr, int rec_x = 0, double* obj = nullptr,
+                       int obj_kind = 0);
 // The mode of a step of this lattice: MODE_OPEN when the open borders can be
 // set inside the step kernel (the outlet column and the one before it share
 // a 64-node tile, i.e. nx % 64 != 1), else MODE_STEP.

@@ -92,7 +92,8 @@ template <class DS, int SM, bool MASK, int FORCE, int MODE>
 __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc& L,
                                             const float* __restrict__ src,
                                             float* __restrict__ dst,
-                                            float* __restrict__ fields, int x, int y) {
+                                            float* __restrict__ fields, int x, int y,
+                                            double& obj) {
   constexpr int Q = DS::Q;
   const int nx = L.nx, ny = L.ny;
   const int row = L.row;   // nx rounded up to 64
@@ -184,6 +185,23 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
   bool ok = landau3<DS::planar>(T00, T0x, T0y, Txx, Txy, Tyy, fr);
   const double n = fr.u0 * J0 - fr.ux * Jx - fr.uy * Jy;
   ok = ok && (n == n);
+
+  // objective density of the streamed state (fluid nodes): the charge
+  // current J^x, or pi:pi with pi = T^{kl} - T_eq^{kl} (spatial block)
+  if constexpr (MODE == MODE_OBJ) {
+    if (!solid && ok) {
+      if (a.obj_kind == 0) {
+        obj = Jx;
+      } else {
+        const double e43 = (4.0 / 3.0) * fr.eps, e3 = fr.eps / 3.0;
+        const double pxx = Txx - (e43 * fr.ux * fr.ux + e3);
+        const double pyy = Tyy - (e43 * fr.uy * fr.uy + e3);
+        const double pxy = Txy - e43 * fr.ux * fr.uy;
+        const double pzz = (T00 - Txx - Tyy) - e3;
+        obj = pxx * pxx + pyy * pyy + 2.0 * pxy * pxy + pzz * pzz;
+      }
+    }
+  }
 
   if constexpr (MODE == MODE_FIELDS) {
     const double vals[RLB_FIELD_COUNT] = {
@@ -351,10 +369,18 @@ __global__ __launch_bounds__(64 * TY, DS::Q == 26 ? 12 / TY : 1) void tile_kerne
     const int ty = in / w;
     const int x = (st * sw + (in - ty * w)) * 64 + lane;
     const int y = __builtin_amdgcn_readfirstlane(ty * TY + row);
+    double obj = 0.0;
     if (x < L.nx && y < L.ny)
       node_update<DS, SM, MASK, FORCE, MODE>(a.sh, L, L.state[a.parity],
                                                const_cast<float*>(L.state[a.parity ^ 1]),
-                                               a.fields, x, y);
+                                               a.fields, x, y, obj);
+    if constexpr (MODE == MODE_OBJ) {
+      if (y < L.ny) {   // wave-uniform; every lane takes part (0 past nx)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) obj += __shfl_xor(obj, o, 64);
+        if (lane == 0) a.sh.obj[(size_t)y * L.tiles_x + (x >> 6)] += obj;
+      }
+    }
   }
 }
 
@@ -454,6 +480,8 @@ StepShared shared_of(const rlb_lattice* lat) {
   a.field_mask = 0;
   a.rec = nullptr;
   a.rec_x = 0;
+  a.obj = nullptr;
+  a.obj_kind = 0;
   return a;
 }
 
@@ -494,6 +522,10 @@ static void by_rows(int ty, const TileArgs& a, int grid, hipStream_t s) {
 template <class DS, int SM, bool MASK>
 static void by_force(int mode, int force, int ty, const TileArgs& a, int grid, hipStream_t s) {
   if (mode == MODE_FIELDS) return by_rows<DS, SM, MASK, FORCE_NONE, MODE_FIELDS>(4, a, grid, s);
+  if (mode == MODE_OBJ) {   // the adjoint's forward: stirring-basis force, cfl <= 1, 3D set
+    if constexpr (!DS::planar && SM != SM_WIDE) by_rows<DS, SM, MASK, FORCE_STIR, MODE_OBJ>(ty, a, grid, s);
+    return;
+  }
   if (mode == MODE_OPEN) {   // open borders: not with the planar set or cfl > 1 (host checks)
     if constexpr (!DS::planar && SM != SM_WIDE) {
       if (force == FORCE_NONE) return by_rows<DS, SM, MASK, FORCE_NONE, MODE_OPEN>(ty, a, grid, s);
@@ -557,12 +589,15 @@ hipError_t launch_tiles(int Q, int sm, bool mask, int mode, int force_mode,
 }
 
 hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode, int parity,
-                       float* fields, uint32_t field_mask, double* rec, int rec_x) {
+                       float* fields, uint32_t field_mask, double* rec, int rec_x, double* obj,
+                       int obj_kind) {
   TileArgs a;
   a.sh = shared_of(lat);
   a.sh.field_mask = field_mask;
   a.sh.rec = rec;
   a.sh.rec_x = rec_x;
+  a.sh.obj = obj;
+  a.sh.obj_kind = obj_kind;
   a.lats = lat->d_desc;
   a.tile_lat = nullptr;
   a.parity = parity;
