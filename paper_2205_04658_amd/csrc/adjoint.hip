@@ -131,6 +131,13 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
       lg[p] = 0.0f;
     }
   });
+  // this node's force and accumulators, loaded with the populations so
+  // that their latency overlaps the pulls (the accumulators would otherwise
+  // be read after the adjoint's stores, at the end of the critical path)
+  const gfloat* frc = (const gfloat*)a.force + (int64_t)y * a.row + x;
+  const float frx = frc[0], fry = frc[a.pitch];
+  double2 af = a.acc_f[node];
+  double at = a.acc_itau[node];
   char* out = (char*)a.mu_out + nb.r[1] + nb.c[1];
   auto put = [&](int plane, float v) { *(float*)(out + plane * 256) = v; };
 
@@ -162,9 +169,8 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   const EqCoef ec = eq_coef(fr, n, sh.eps_ref, sh.n_ref, DS::kappa);
   const float ux = (float)fr.ux, uy = (float)fr.uy, u0 = (float)fr.u0;
   const float itau = sh.inv_tau;
-  const gfloat* frc = (const gfloat*)a.force + (int64_t)y * a.row + x;
-  const float Fx = sh.fx + frc[0];
-  const float Fy = sh.fy + frc[a.pitch];
+  const float Fx = sh.fx + frx;
+  const float Fy = sh.fy + fry;
   float q3xxx = 0, q3xxy = 0, q3xyy = 0, q3yyy = 0, q3xzz = 0, q3yzz = 0;
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
@@ -312,11 +318,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
     put(Q + p, mg[p] + b0 + (float)vx * bx + (float)vy * by);
   });
   // parameter adjoints of this node
-  double2 af = a.acc_f[node];
   af.x += (double)lFx;
   af.y += (double)lFy;
   a.acc_f[node] = af;
-  a.acc_itau[node] += (double)litau;
+  a.acc_itau[node] = at + (double)litau;
 }
 
 // Objective density summed over fluid nodes, added to a per-block running
