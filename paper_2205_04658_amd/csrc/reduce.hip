@@ -78,11 +78,23 @@ __global__ __launch_bounds__(256) void totals_final_kernel(const double* __restr
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Plain device copy for bandwidth calibration: each thread moves four
+// 16-byte items, all four loads issued before the (non-temporal) stores.
+constexpr int kCopyUnroll = 4;
 __global__ __launch_bounds__(256) void copy_kernel(const f32x4* __restrict__ s,
                                                    f32x4* __restrict__ d, size_t n) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    __builtin_nontemporal_store(s[i], d + i);
+  const size_t base = (size_t)blockIdx.x * (256 * kCopyUnroll) + threadIdx.x;
+  f32x4 v[kCopyUnroll];
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const size_t i = base + (size_t)u * 256;
+    if (i < n) v[u] = s[i];
+  }
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const size_t i = base + (size_t)u * 256;
+    if (i < n) __builtin_nontemporal_store(v[u], d + i);
+  }
 }
 
 hipError_t launch_totals(const rlb_lattice* lat, const float* state,
@@ -110,7 +122,9 @@ hipError_t launch_totals(const rlb_lattice* lat, const float* state,
 
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 16;
-  hipLaunchKernelGGL(copy_kernel, dim3(4096), dim3(256), 0, s,
+  if (n == 0) return hipSuccess;
+  const size_t blocks = (n + 256 * kCopyUnroll - 1) / (256 * kCopyUnroll);
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                      (const f32x4*)src, (f32x4*)dst, n);
   return hipGetLastError();
 }
