@@ -1,0 +1,115 @@
+"""Edge cases of the step on the GPU against the FP64 oracle: the smallest
+lattice (4 x 4, one tile with 60 idle lanes, stirring at |k| = 1), a last
+tile holding a single column (65 x 9, walls, body force), every node solid,
+the fastest stable uniform flow and an unstable one (reported as a
+failure), and a zero-step call."""
+import numpy as np
+import pytest
+
+from oracle import rlb
+from paper_2205_04658_amd import workloads
+from rlbtest import compare, fold, need_gpu, oracle_run, scales
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def lattice(f, tau, **kw):
+    from paper_2205_04658_amd.rlb import Lattice
+    ny, nx = f["eps"].shape
+    lat = Lattice(nx, ny, tau, **kw)
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    return lat
+
+
+def test_smallest_lattice_with_stirring():
+    torch = need_gpu()
+    f = workloads.random_fields(4, 4, seed=41, beta=0.02)
+    lat = lattice(f, 0.7)
+    stir = (0.5, 1.5, 1e-3, 5)
+    lat.set_stirring(*stir)
+    lat.step(30)
+    F, G = oracle_run(f, 30, 0.7, stir=stir)
+    err = compare(lat.fields(), rlb.fields(F, G), scales(beta=0.02))
+    assert max(err.values()) < TOL, err
+
+
+def test_last_tile_with_one_column():
+    torch = need_gpu()
+    nx, ny = 65, 9
+    f = workloads.random_fields(nx, ny, seed=42, beta=0.02)
+    lat = lattice(f, 0.75, walls=True)
+    lat.set_body_force(2e-4, -1e-4)
+    lat.step(25)
+    solid = np.zeros((ny, nx), bool)
+    solid[0] = solid[-1] = True
+    F, G = oracle_run(f, 25, 0.75, solid=solid, body=(2e-4, -1e-4))
+    err = compare(lat.fields(), rlb.fields(F, G, solid=solid), scales(beta=0.02))
+    assert max(err.values()) < TOL, err
+
+
+def test_every_node_solid():
+    """Pure bounce-back of streamed populations: the planes follow the
+    oracle, every field reads zero and the totals stay put."""
+    torch = need_gpu()
+    nx, ny = 16, 8
+    f = workloads.random_fields(nx, ny, seed=43, beta=0.03)
+    lat = lattice(f, 0.8)
+    solid = np.ones((ny, nx), bool)
+    lat.set_obstacles(solid.astype(np.uint8))
+    t0 = lat.conserved()
+    lat.step(7)
+    lat.sync()
+    F, G = oracle_run(f, 7, 0.8, solid=solid)
+    pf, pg = lat.planes()
+    w = rlb.W[:, None, None]
+    assert np.abs(pf.double().cpu().numpy() - fold(F - w * 1.0)).max() < 1e-7
+    assert np.abs(pg.double().cpu().numpy() - fold(G - w * 0.1)).max() < 1e-8
+    g = lat.fields(["eps", "beta_x", "n"])
+    assert all(float(v.abs().max()) == 0.0 for v in g.values())
+    t1 = lat.conserved()
+    assert abs(t1[0] - t0[0]) < 1e-9 * t0[0] and abs(t1[3] - t0[3]) < 1e-9 * t0[3]
+
+
+def test_fast_uniform_flow_is_a_fixed_point():
+    """|beta| = 0.4 (the fastest uniform flow this tau keeps stable: from
+    0.5 on, rounding-level perturbations grow in the oracle as well)."""
+    torch = need_gpu()
+    nx, ny = 64, 8
+    f = workloads.uniform(nx, ny, 1.0, 0.1)
+    f["bx"][:] = 0.24
+    f["by"][:] = 0.32
+    lat = lattice(f, 0.9)
+    lat.step(100)
+    g = lat.fields()
+    F, G = oracle_run(f, 0, 0.9)
+    err = compare(g, rlb.fields(F, G), scales(beta=0.4, n=0.1 * 1.1))
+    assert max(err.values()) < TOL, err
+
+
+def test_unstable_fast_flow_is_reported():
+    """|beta| = 0.7 is linearly unstable at this tau (the oracle loses its
+    Landau frame at step 10 from this 1e-6 perturbation); the GPU run
+    must end in a reported failure, not silently."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import ELANDAU, ENONFINITE, RLBError
+    f = workloads.random_fields(64, 8, seed=45, beta=0.0, deps=1e-6, dn=0.0)
+    f["bx"][:] += 0.7
+    lat = lattice(f, 0.9)
+    lat.step(200)
+    with pytest.raises(RLBError) as e:
+        lat.sync()
+    assert e.value.status in (ELANDAU, ENONFINITE)
+
+
+def test_zero_steps_change_nothing():
+    torch = need_gpu()
+    f = workloads.random_fields(40, 12, seed=44)
+    lat = lattice(f, 0.7)
+    lat.set_stirring(1, 3, 1e-4, 2)
+    lat.step(3)
+    before = lat.save_state().cpu()
+    lat.step(0)
+    lat.sync()
+    assert lat.step_count == 3
+    assert torch.equal(lat.save_state().cpu(), before)
