@@ -4,14 +4,17 @@
 // recorded at the outflow border over time and along the channel, and its
 // fluctuations are examined in frequency and wave-number space).
 //
-// Borders, applied after every step to the new state:
+// Borders of the new state after every step:
 //   * velocity inlet, column 0: equilibrium at the prescribed 3-velocity
 //     and charge density, with the energy density of column 1;
 //   * pressure outlet, column nx-1: equilibrium at the prescribed energy
 //     density, with the velocity and charge density of column nx-2.
 // The adjacent columns' frames come from Landau matching of their stored
 // (post-collision) moments.  Streaming stays periodic: the wrapped values
-// reach only the two border columns, which this kernel overwrites.
+// reach only the two border columns, which are overwritten.  The step
+// kernel sets the borders itself (open_borders in step.hip, same
+// arithmetic); the kernel here serves widths with nx % 64 == 1, where the
+// outlet column and column nx-2 fall in different 64-node tiles.
 #include <algorithm>
 
 #include "internal.hpp"

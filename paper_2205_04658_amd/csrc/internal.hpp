@@ -26,12 +26,13 @@ enum : uint32_t { ERR_LANDAU = 1u, ERR_NONFINITE = 2u };
 
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
-// Step-kernel modes: a step, the field read-out, or a step that also sets
-// the open x borders of the new state (velocity inlet, pressure outlet).
-// MODE_OBJ: a step that also adds the adjoint objective's density of the
-// state it streams to per-wavefront slots (StepShared::obj).
+// Step-kernel modes: a step; the field read-out; a step that also sets the
+// open x borders of the new state (velocity inlet, pressure outlet); a step
+// that also adds the adjoint objective's density of the state it streams
+// to per-wavefront slots (StepShared::obj).
 enum StepMode : int { MODE_STEP = 0, MODE_FIELDS = 1, MODE_OPEN = 2, MODE_OBJ = 3 };
-// Force modes: none, uniform body force, body force + k-shell stirring.
+// Force modes: none, uniform body force, body force + force planes (the
+// k-shell stirring, or the adjoint's static basis).
 enum ForceMode : int { FORCE_NONE = 0, FORCE_BODY = 1, FORCE_STIR = 2 };
 
 // Parameters shared by every lattice of one step launch.

@@ -1,19 +1,23 @@
 // The fused RLB step for gfx950: pull-stream -> moments -> Landau matching
 // -> equilibrium -> Anderson-Witting relaxation + driving term, with
 // bounce-back at solid nodes; plus the field read-out and initialisation
-// kernels that reuse its pieces.
+// kernels that reuse its pieces.  Modes of the tile kernel: a step; the
+// field read-out; a step that also sets the open x borders (and may record
+// a column's current); a step that also sums the adjoint's objective.
 //
 // Layout: node bricks (brick.hpp): each lattice row is a run of 64-node
 // bricks holding the 2Q planes of their nodes (F planes 0..Q-1, then G
 // planes Q..2Q-1).  The stirring force keeps two plain [ny][row] planes.
-// One thread
-// per node; a tile is 64 x TY nodes, one wavefront per row, so row-uniform
-// quantities are scalar.  A launch walks a list of tiles that may span many
-// lattices (the batched path): each tile names its lattice, whose
-// descriptor is read with scalar loads.  The eight XCDs each take a
-// contiguous band of the tile list, so vertically adjacent tiles, which
-// share halo rows, run on the same XCD and meet in its L2.  The grid is
-// either one workgroup per tile or a persistent set of workgroups per CU.
+// One thread per node; a tile is 64 x TY nodes, one wavefront per row, so
+// row-uniform quantities are scalar.  A launch walks a list of tiles that
+// may span many lattices (the batched path): each tile names its lattice,
+// whose descriptor is read with scalar loads.  A lattice's tiles are
+// ordered in vertical strips a few tiles wide and the eight XCDs each take
+// a contiguous band of that order, so tiles that share halo rows and
+// columns run on the same XCD close together and meet in its L2.  The grid
+// is either one workgroup per tile or a persistent set of workgroups per
+// CU.
+
 #include <algorithm>
 
 #include "internal.hpp"
