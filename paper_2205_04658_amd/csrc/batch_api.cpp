@@ -79,7 +79,6 @@ rlb_status bfail(rlb_status s, const char* fmt, ...) {
     if (_e != hipSuccess) return bfail(RLB_EDEVICE, "%s: %s", what, hipGetErrorString(_e)); \
   } while (0)
 
-constexpr size_t kBatchHeader = 4096;
 
 struct BatchLayout {
   std::vector<size_t> mem_off, mem_bytes;
