@@ -79,7 +79,6 @@ rlb_status bfail(rlb_status s, const char* fmt, ...) {
     if (_e != hipSuccess) return bfail(RLB_EDEVICE, "%s: %s", what, hipGetErrorString(_e)); \
   } while (0)
 
-
 struct BatchLayout {
   std::vector<size_t> mem_off, mem_bytes;
   size_t desc_off, tile_off, err_off, total;
