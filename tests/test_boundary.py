@@ -108,4 +108,10 @@ def test_null_handle_calls(L):
     assert L.rlb_philox(0, 0, 0, -1, None, None) == B.EINVAL
     assert L.rlb_copy_probe(ctypes.c_void_p(256), ctypes.c_void_p(512 + 4), 32, None) == B.EINVAL
     assert L.rlb_copy_probe(ctypes.c_void_p(256), ctypes.c_void_p(512), 30, None) == B.EINVAL
+    assert L.rlb_use_graph(None, 2) == B.EINVAL
+    n = ctypes.c_size_t(7)
+    assert L.rlb_record_workspace_bytes(None, 16, ctypes.byref(n)) == B.EINVAL and n.value == 7
+    assert L.rlb_record_current(None, 4, 0, None, None, 0) == B.EINVAL
+    assert L.rlb_batch_set_open_borders(None, 0.1, 0.0, 0.1, 1.0) == B.EINVAL
+    assert L.rlb_set_open_borders(None, 0.1, 0.0, 0.1, 1.0) == B.EINVAL
     assert b"null" in L.rlb_last_error() or len(L.rlb_last_error()) > 0
