@@ -1,5 +1,7 @@
 """Spherical momentum set and angular polynomials (oracle).
 
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
 Ch. 3, "Boltzmann to Lattice Boltzmann": the momentum directions come from a
 quadrature that is exact for angular integrals (dOmega / 4 pi) of the
 polynomials used; the dissertation names the set a spherical "D3Q27" (Ch. 4,
