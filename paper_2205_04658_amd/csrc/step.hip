@@ -349,7 +349,7 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
 // alone the compiler takes ~200 registers and 2 waves, measured 4% slower
 // at 4096^2.
 template <class DS, int SM, bool MASK, int FORCE, int MODE, int TY>
-__global__ __launch_bounds__(64 * TY, DS::Q == 26 ? 12 / TY : 1) void tile_kernel(const TileArgs a) {
+__global__ __launch_bounds__(64 * TY, DS::Q == 26 ? 3 : 1) void tile_kernel(const TileArgs a) {
   const int xcd = blockIdx.x & 7;
   const int per = gridDim.x >> 3;
   const int lo = xcd * a.tiles_per_xcd;
