@@ -204,7 +204,8 @@ def run_part2_sweep(torch, rlb, workloads, steps=1000, warmup=50):
     """The Part II placement sweep as one batch: six 1024 x 256 channels
     (the single impurity, and the pair at each of the five separations
     1.68 ... 8.39 um, 25 degrees), shared inlet/outlet and tau, one launch
-    per step over all six, replayed from a hipGraph."""
+    per step over all six, replayed from a hipGraph; then the same number
+    of steps recording each channel's j(t) (one column launch per step)."""
     c = workloads.PART2
     nx, ny = c["nx"], c["ny"]
     placements = [workloads.part2_discs()] + [workloads.part2_discs(d) for d in c["separations_um"]]
@@ -227,8 +228,18 @@ def run_part2_sweep(torch, rlb, workloads, steps=1000, warmup=50):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     B.sync()
+    # the same run recording every channel's j(t) at the column before its outlet
+    series = torch.zeros((len(placements), steps), dtype=torch.float64, device=B.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.record_current(steps, -2, out=series)
+    torch.cuda.synchronize()
+    wall_j = time.perf_counter() - t0
+    B.sync()
+    peaks = [int(rlb.power_spectrum(series[b])[1:].argmax()) + 1 for b in range(len(placements))]
     out = dict(channels=len(placements), cells=cells, steps=steps,
                mlups=cells * steps / wall / 1e6, ms_per_step=wall / steps * 1e3,
+               mlups_with_j=cells * steps / wall_j / 1e6, j_peak_bins=peaks,
                shape=B.launch_shape())
     out["achieved_gbs"] = (2 * 2 * B.info()["planes"] * 4 + 1) * cells / (wall / steps) / 1e9
     B.close()

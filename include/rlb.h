@@ -398,6 +398,30 @@ rlb_status rlb_batch_set_open_borders(rlb_batch* batch, double bx, double by, do
  * otherwise RLB_ESTATE. */
 rlb_status rlb_batch_step(rlb_batch* batch, int64_t nsteps);
 
+/* Bytes of the rlb_batch_record_current workspace that holds `chunk` steps
+ * (1 <= chunk <= 32768): chunk * (sum of the members' ny) float64,
+ * rounded up to 256. */
+rlb_status rlb_batch_record_workspace_bytes(const rlb_batch* batch, int32_t chunk, size_t* bytes);
+
+/* nsteps batched steps that also record every member's current density
+ * (Ch. 6: j(t) of each impurity placement): d_series[b * stride + t] = j
+ * of member b's state before step t+1 at column x, t = 0 .. nsteps-1,
+ * bitwise the series rlb_record_current gives for an open-channel member
+ * stepped alone, and otherwise rlb_column_current before each step.  x >= 0 names the same column in every member; x < 0 counts
+ * from each member's last column (-2: the column before the outlet,
+ * x + nx_b).  Open-channel batches (RLB_OPEN_X) record in the step kernel
+ * (one launch per step, plus one averaging launch per chunk of steps);
+ * otherwise a column launch (one workgroup per member) precedes each
+ * step.  Steps launch kernel by kernel, never as graphs.
+ * d_work: a 256-byte aligned device workspace of `bytes`
+ * (rlb_batch_record_workspace_bytes), holding up to 32768 steps at a time
+ * (RLB_ENOMEM below one).  RLB_EINVAL for a column outside a member,
+ * stride < nsteps, or a null or misaligned d_series (8 bytes) or d_work;
+ * RLB_EUNSUPPORTED for cfl > 1; RLB_ESTATE as rlb_batch_step.  Nothing is
+ * checked past the column when nsteps == 0. */
+rlb_status rlb_batch_record_current(rlb_batch* batch, int64_t nsteps, int32_t x,
+                                    double* d_series, int64_t stride, void* d_work, size_t bytes);
+
 /* Wait for queued work; report device failures of batched steps. */
 rlb_status rlb_batch_sync(rlb_batch* batch);
 

@@ -286,7 +286,7 @@ rlb_status rlb_create(const rlb_params* p, void* d_workspace, size_t bytes,
   lat->desc.tiles_x = (p->nx + 63) / 64;
   lat->desc.tile_begin = 0;
   lat->desc.row = row;
-  lat->desc.pad = 0;
+  lat->desc.rec_row = 0;
   lat->result = (double*)(lat->ws + w.misc_off + 128);
   if (Q == 17) fill_taps<Dir17>(lat);
   else if (Q == 12) fill_taps<DirP12>(lat);

@@ -42,6 +42,7 @@ struct rlb_batch {
   LaunchShape shape;
   int ntiles;
   int table_rows;          // tile_rows the table was built for (0 = none)
+  int64_t rec_rows;        // rows of all members (recorded current density)
   double fx, fy;
   int64_t step;
   // graph
@@ -61,6 +62,8 @@ struct rlb_batch {
 namespace {
 
 thread_local std::string g_berr;
+
+constexpr int kBatchRecChunk = 32768;   // steps per row-means launch (grid y)
 
 rlb_status bfail(rlb_status s, const char* fmt, ...) {
   char buf[512];
@@ -90,7 +93,7 @@ rlb_status batch_layout(const rlb_params* p, int count, const int32_t* nx, const
   if (count < 1 || count > 65536) return bfail(RLB_EINVAL, "count must be in [1, 65536]");
   if (!nx || !ny) return bfail(RLB_EINVAL, "size arrays are null");
   size_t off = 0;
-  int64_t tiles = 0;
+  int64_t tiles = 0, rows = 0;
   for (int b = 0; b < count; ++b) {
     // open borders in a batch are set inside the step kernel, which needs the
     // outlet column and the one before it in one 64-node tile
@@ -106,8 +109,10 @@ rlb_status batch_layout(const rlb_params* p, int count, const int32_t* nx, const
     L.mem_bytes.push_back(n);
     off += align_up(n);
     tiles += (int64_t)((nx[b] + 63) / 64) * ny[b];   // tile_rows = 1 is the largest table
+    rows += ny[b];
   }
   if (tiles >= (int64_t)1 << 31) return bfail(RLB_EINVAL, "too many tiles");
+  if (rows >= (int64_t)1 << 31) return bfail(RLB_EINVAL, "too many rows");
   L.desc_off = off; off += align_up(sizeof(LatDesc) * (size_t)count);
   L.tile_off = off; off += align_up(sizeof(int32_t) * (size_t)tiles);
   L.err_off = off; off += align_up(64);
@@ -119,10 +124,12 @@ rlb_status build_tables(rlb_batch* B, int tile_rows) {
   if (B->table_rows == tile_rows) return RLB_OK;
   B->h_desc.resize(B->count);
   B->h_tile_lat.clear();
-  int begin = 0;
+  int begin = 0, rec_row = 0;
   for (int b = 0; b < B->count; ++b) {
     LatDesc d = B->mem[b]->desc;
     d.tile_begin = begin;
+    d.rec_row = rec_row;
+    rec_row += d.ny;
     B->h_desc[b] = d;
     const int n = tiles_of(d.nx, d.ny, tile_rows);
     B->h_tile_lat.insert(B->h_tile_lat.end(), (size_t)n, b);
@@ -171,11 +178,21 @@ TileArgs tile_args(const rlb_batch* B, int parity) {
   return a;
 }
 
-hipError_t launch_batch_step(const rlb_batch* B, int parity, bool mask, int force) {
+// rec: J^x of column rec_x of every member, written row by row (see
+// records_current) into rec[rec_row + y]
+hipError_t launch_batch_step(const rlb_batch* B, int parity, bool mask, int force,
+                             double* rec = nullptr, int rec_x = 0) {
   const int mode = (B->p.flags & RLB_OPEN_X) ? MODE_OPEN : MODE_STEP;
-  return launch_tiles(B->Q, stream_mode(B->p.cfl), mask, mode, force, tile_args(B, parity),
-                      B->shape, B->num_cu, B->stream);
+  TileArgs a = tile_args(B, parity);
+  a.sh.rec = rec;
+  a.sh.rec_x = rec_x;
+  return launch_tiles(B->Q, stream_mode(B->p.cfl), mask, mode, force, a, B->shape, B->num_cu,
+                      B->stream);
 }
+
+// the open-channel step kernels write the recorded column themselves
+// (every member has nx % 64 != 1)
+bool records_current(const rlb_batch* B) { return (B->p.flags & RLB_OPEN_X) != 0; }
 
 rlb_status check_batch(const rlb_batch* B) {
   if (!B) return bfail(RLB_EINVAL, "batch is null");
@@ -231,6 +248,7 @@ rlb_status rlb_batch_create(const rlb_params* p, int32_t count, const int32_t* h
   B->stream = (hipStream_t)hip_stream;
   B->shape = LaunchShape{4, 0, 16};
   B->graph_steps = 16;
+  for (int b = 0; b < count; ++b) B->rec_rows += h_ny[b];
   for (int b = 0; b < count; ++b) {
     rlb_params q = *p;
     q.nx = h_nx[b];
@@ -387,6 +405,73 @@ rlb_status rlb_batch_step(rlb_batch* B, int64_t nsteps) {
     advance(B, 1);
     parity ^= 1;
     --left;
+  }
+  if (B->timing) {
+    BHIP(hipEventRecord(B->ev[1], B->stream), "event record");
+    BHIP(hipEventSynchronize(B->ev[1]), "event synchronize");
+    float ms = 0.f;
+    BHIP(hipEventElapsedTime(&ms, B->ev[0], B->ev[1]), "event elapsed");
+    B->timed_ms += ms;
+    B->timed_steps += nsteps;
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_batch_record_workspace_bytes(const rlb_batch* B, int32_t chunk, size_t* bytes) {
+  if (rlb_status s = check_batch(B)) return s;
+  if (!bytes) return bfail(RLB_EINVAL, "bytes is null");
+  if (chunk < 1 || chunk > kBatchRecChunk) return bfail(RLB_EINVAL, "chunk must be in [1, %d]", kBatchRecChunk);
+  *bytes = align_up((size_t)chunk * (size_t)B->rec_rows * sizeof(double));
+  return RLB_OK;
+}
+
+rlb_status rlb_batch_record_current(rlb_batch* B, int64_t nsteps, int32_t x, double* d_series,
+                                    int64_t stride, void* d_work, size_t bytes) {
+  if (rlb_status s = check_batch(B)) return s;
+  if (nsteps < 0) return bfail(RLB_EINVAL, "nsteps must be >= 0");
+  for (int b = 0; b < B->count; ++b) {
+    const int nx = B->mem[b]->p.nx;
+    if (x >= nx || x < -nx)
+      return bfail(RLB_EINVAL, "column %d outside member %d (nx = %d)", x, b, nx);
+  }
+  if (B->p.cfl > 1.0) return bfail(RLB_EUNSUPPORTED, "the column current supports cfl <= 1");
+  if (nsteps == 0) return RLB_OK;
+  if (stride < nsteps) return bfail(RLB_EINVAL, "stride %lld is below nsteps %lld", (long long)stride,
+                                    (long long)nsteps);
+  if (!d_series || (uintptr_t)d_series % 8)
+    return bfail(RLB_EINVAL, "d_series must be an 8-byte aligned device pointer");
+  if (!d_work || (uintptr_t)d_work % kAlign)
+    return bfail(RLB_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  const size_t step_bytes = (size_t)B->rec_rows * sizeof(double);
+  const int64_t chunk = (int64_t)std::min<size_t>(bytes / step_bytes, kBatchRecChunk);
+  if (chunk < 1)
+    return bfail(RLB_ENOMEM, "record workspace has %zu bytes, needs at least %zu", bytes, step_bytes);
+  int parity = 0;
+  if (rlb_status s = member_parity(B, &parity)) return s;
+  const bool mask = any_solid(B);
+  const int force = force_mode(B);
+  if (B->timing) BHIP(hipEventRecord(B->ev[0], B->stream), "event record");
+  if (records_current(B)) {
+    double* rows = (double*)d_work;
+    for (int64_t t0 = 0; t0 < nsteps; t0 += chunk) {
+      const int64_t cnt = std::min(chunk, nsteps - t0);
+      for (int64_t i = 0; i < cnt; ++i) {
+        BHIP(launch_batch_step(B, parity, mask, force, rows + i * B->rec_rows, x), "batch step");
+        advance(B, 1);
+        parity ^= 1;
+      }
+      BHIP(launch_batch_row_means(B->d_desc, B->count, rows, B->rec_rows, (int)cnt, d_series + t0,
+                                  stride, B->stream), "row means");
+    }
+  } else {   // the column kernel before each step
+    const StepShared sh = shared_of(B->mem[0]);
+    for (int64_t t = 0; t < nsteps; ++t) {
+      BHIP(launch_batch_column_current(sh, B->Q, B->d_desc, B->count, parity, B->p.cfl == 1.0, mask,
+                                       x, stride, d_series + t, B->stream), "column current");
+      BHIP(launch_batch_step(B, parity, mask, force), "batch step");
+      advance(B, 1);
+      parity ^= 1;
+    }
   }
   if (B->timing) {
     BHIP(hipEventRecord(B->ev[1], B->stream), "event record");

@@ -78,12 +78,10 @@ __global__ __launch_bounds__(256) void open_borders_kernel(float* __restrict__ s
 
 // j at column x: the mean over the column's nodes of the charge current
 // J^x of the streamed populations (solid nodes count as zero), one
-// workgroup, fixed summation order.
+// workgroup of 256, fixed summation order; the result is valid in thread 0.
 template <class DS, bool UNIT, bool MASK>
-__global__ __launch_bounds__(256) void column_current_kernel(const float* __restrict__ st,
-                                                             const uint8_t* __restrict__ mask,
-                                                             const StepShared sh, int nx, int ny,
-                                                             int row, int x, double* out) {
+__device__ double column_mean(const float* __restrict__ st, const uint8_t* __restrict__ mask,
+                              const StepShared& sh, int nx, int ny, int row, int x) {
   constexpr int Q = DS::Q;
   double acc = 0.0;
   for (int y = threadIdx.x; y < ny; y += blockDim.x) {
@@ -102,7 +100,30 @@ __global__ __launch_bounds__(256) void column_current_kernel(const float* __rest
   __shared__ double red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) *out = ((red[0] + red[1]) + (red[2] + red[3])) / (double)ny;
+  return ((red[0] + red[1]) + (red[2] + red[3])) / (double)ny;
+}
+
+template <class DS, bool UNIT, bool MASK>
+__global__ __launch_bounds__(256) void column_current_kernel(const float* __restrict__ st,
+                                                             const uint8_t* __restrict__ mask,
+                                                             const StepShared sh, int nx, int ny,
+                                                             int row, int x, double* out) {
+  const double j = column_mean<DS, UNIT, MASK>(st, mask, sh, nx, ny, row, x);
+  if (threadIdx.x == 0) *out = j;
+}
+
+// The same column mean for every lattice of a batch, one workgroup per
+// lattice: out[b * stride] for lattice b at column x (x < 0 counts from
+// that lattice's last column, x + nx), state copy `parity`.
+template <class DS, bool UNIT, bool MASK>
+__global__ __launch_bounds__(256) void batch_column_current_kernel(const LatDesc* __restrict__ lats,
+                                                                   const StepShared sh, int parity,
+                                                                   int x, int64_t stride,
+                                                                   double* out) {
+  const LatDesc d = lats[blockIdx.x];
+  const int xc = x < 0 ? x + d.nx : x;   // in range: checked on the host
+  const double j = column_mean<DS, UNIT, MASK>(d.state[parity], d.mask, sh, d.nx, d.ny, d.row, xc);
+  if (threadIdx.x == 0) out[(int64_t)blockIdx.x * stride] = j;
 }
 
 // ---------------------------------------------------------------------------
@@ -187,6 +208,27 @@ static void column_go(const rlb_lattice* lat, const StepShared& sh, int x, doubl
 #undef RLB_COL
 }
 
+template <class DS>
+static void batch_column_go(const StepShared& sh, const LatDesc* lats, int count, int parity,
+                            bool unit, bool mask, int x, int64_t stride, double* out,
+                            hipStream_t stream) {
+#define RLB_BCOL(U, M)                                                                    \
+  hipLaunchKernelGGL((batch_column_current_kernel<DS, U, M>), dim3(count), dim3(256), 0, \
+                     stream, lats, sh, parity, x, stride, out)
+  if (unit) { if (mask) RLB_BCOL(true, true); else RLB_BCOL(true, false); }
+  else { if (mask) RLB_BCOL(false, true); else RLB_BCOL(false, false); }
+#undef RLB_BCOL
+}
+
+hipError_t launch_batch_column_current(const StepShared& sh, int Q, const LatDesc* lats, int count,
+                                       int parity, bool unit, bool mask, int x, int64_t stride,
+                                       double* out, hipStream_t stream) {
+  if (Q == 17) batch_column_go<Dir17>(sh, lats, count, parity, unit, mask, x, stride, out, stream);
+  else if (Q == 12) batch_column_go<DirP12>(sh, lats, count, parity, unit, mask, x, stride, out, stream);
+  else batch_column_go<Dir26>(sh, lats, count, parity, unit, mask, x, stride, out, stream);
+  return hipGetLastError();
+}
+
 hipError_t launch_column_current(const rlb_lattice* lat, int x, double* out) {
   const StepShared sh = shared_of(lat);
   if (lat->Q == 17) column_go<Dir17>(lat, sh, x, out);
@@ -195,11 +237,9 @@ hipError_t launch_column_current(const rlb_lattice* lat, int x, double* out) {
   return hipGetLastError();
 }
 
-// One workgroup per row of `rows`: out[t] = (sum_y rows[t][y]) / ny, summed
-// in the order of the column current kernel.
-__global__ __launch_bounds__(256) void row_means_kernel(const double* __restrict__ rows, int ny,
-                                                        double* __restrict__ out) {
-  const double* r = rows + (size_t)blockIdx.x * ny;
+// Mean of r[0 .. ny) by one workgroup of 256 in a fixed order; valid in
+// thread 0.
+__device__ double row_mean(const double* __restrict__ r, int ny) {
   double acc = 0.0;
   for (int y = threadIdx.x; y < ny; y += blockDim.x) acc += r[y];
 #pragma unroll
@@ -207,12 +247,37 @@ __global__ __launch_bounds__(256) void row_means_kernel(const double* __restrict
   __shared__ double red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = ((red[0] + red[1]) + (red[2] + red[3])) / (double)ny;
+  return ((red[0] + red[1]) + (red[2] + red[3])) / (double)ny;
+}
+
+// One workgroup per row of `rows`: out[t] = (sum_y rows[t][y]) / ny.
+__global__ __launch_bounds__(256) void row_means_kernel(const double* __restrict__ rows, int ny,
+                                                        double* __restrict__ out) {
+  const double m = row_mean(rows + (size_t)blockIdx.x * ny, ny);
+  if (threadIdx.x == 0) out[blockIdx.x] = m;
+}
+
+// Workgroup (b, t): lattice b's rows of step t.
+__global__ __launch_bounds__(256) void batch_row_means_kernel(const LatDesc* __restrict__ lats,
+                                                              const double* __restrict__ rows,
+                                                              int64_t total, int64_t stride,
+                                                              double* __restrict__ out) {
+  const LatDesc& d = lats[blockIdx.x];
+  const double m = row_mean(rows + (int64_t)blockIdx.y * total + d.rec_row, d.ny);
+  if (threadIdx.x == 0) out[(int64_t)blockIdx.x * stride + blockIdx.y] = m;
 }
 
 hipError_t launch_row_means(const double* rows, int ny, int count, double* out, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(row_means_kernel, dim3(count), dim3(256), 0, st, rows, ny, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_row_means(const LatDesc* lats, int members, const double* rows, int64_t total,
+                                  int count, double* out, int64_t stride, hipStream_t st) {
+  if (count <= 0 || members <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_row_means_kernel, dim3(members, count), dim3(256), 0, st, lats, rows,
+                     total, stride, out);
   return hipGetLastError();
 }
 

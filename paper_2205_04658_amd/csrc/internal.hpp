@@ -48,7 +48,8 @@ struct StepShared {
   uint32_t* err;          // sticky device error word
   uint32_t field_mask;    // MODE_FIELDS selection
   double* rec;            // non-null (records_current): J^x of the streamed
-  int32_t rec_x;          //   populations at column rec_x written to rec[y] (row y)
+  int32_t rec_x;          //   populations at column rec_x (x < 0: nx + rec_x) written
+                          //   to rec[rec_row + y] (row y of the lattice)
   double* obj;            // MODE_OBJ: slot y * tiles_x + x / 64 += the wavefront's
   int32_t obj_kind;       //   sum of J^x (kind 0) or pi:pi (kind 1) over fluid nodes
 };
@@ -66,7 +67,8 @@ struct LatDesc {
   int32_t tiles_x;        // tiles per row of tiles
   int32_t tile_begin;     // first global tile index of this lattice
   int32_t row;            // row pitch in elements (nx rounded up to 64)
-  int32_t pad;
+  int32_t rec_row;        // first row of this lattice among recorded rows
+                          // (0 alone; a batch's members follow each other)
 };
 
 struct TileArgs {
@@ -258,9 +260,17 @@ hipError_t launch_spectrum(rlb_lattice* lat, int kmax, double kcut, double* out,
                            char* ws);
 hipError_t launch_open_borders(const rlb_lattice* lat, float* state);
 hipError_t launch_column_current(const rlb_lattice* lat, int x, double* out);
+hipError_t launch_batch_column_current(const StepShared& sh, int Q, const LatDesc* lats, int count,
+                                       int parity, bool unit, bool mask, int x, int64_t stride,
+                                       double* out, hipStream_t stream);
 hipError_t launch_power_spectrum(const double* s, int64_t n, double* out, hipStream_t st);
 // out[t] = (1/ny) sum_y rows[t * ny + y], t < count, fixed summation order.
 hipError_t launch_row_means(const double* rows, int ny, int count, double* out, hipStream_t st);
+// out[b * stride + t] = (1/ny_b) sum_y rows[t * total + rec_row_b + y] for the
+// `members` lattices of lats, t < count (<= 32768), in the order of
+// launch_row_means.
+hipError_t launch_batch_row_means(const LatDesc* lats, int members, const double* rows, int64_t total,
+                                  int count, double* out, int64_t stride, hipStream_t st);
 hipError_t launch_init(const rlb_lattice* lat, const float* eps,
                        const float* bx, const float* by, const float* n,
                        float* dst);

@@ -180,7 +180,9 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
   // compiled into the open-channel kernels and the full set's kernels only.
   // The branch splits the kernel's scheduling regions: measured at 4096^2,
   // that costs the folded set's step 8% and saves the full set's 6%
-  if constexpr (MODE == MODE_OPEN || (DS::Q == 26 && MODE != MODE_FIELDS)) {
+  if constexpr (MODE == MODE_OPEN) {
+    if (a.rec != nullptr && x == (a.rec_x < 0 ? a.rec_x + L.nx : a.rec_x)) a.rec[L.rec_row + y] = Jx;
+  } else if constexpr (DS::Q == 26 && MODE != MODE_FIELDS) {
     if (a.rec != nullptr && x == a.rec_x) a.rec[y] = Jx;
   }
 

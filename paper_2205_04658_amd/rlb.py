@@ -33,6 +33,7 @@ SYMBOLS = [
     "rlb_set_launch_shape", "rlb_get_launch_shape", "rlb_autotune",
     "rlb_batch_workspace_bytes", "rlb_batch_create", "rlb_batch_destroy", "rlb_batch_member",
     "rlb_batch_set_body_force", "rlb_batch_set_open_borders", "rlb_batch_step", "rlb_batch_sync", "rlb_batch_info",
+    "rlb_batch_record_workspace_bytes", "rlb_batch_record_current",
     "rlb_batch_set_launch_shape", "rlb_batch_get_launch_shape", "rlb_batch_autotune",
     "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
     "rlb_set_relaxation_time", "rlb_set_relaxation_eta_s", "rlb_adjoint_workspace_bytes",
@@ -121,6 +122,8 @@ def lib():
         "rlb_batch_set_open_borders": [_vp, _d, _d, _d, _d],
         "rlb_batch_step": [_vp, _i64],
         "rlb_batch_sync": [_vp],
+        "rlb_batch_record_workspace_bytes": [_vp, _i32, _P(_sz)],
+        "rlb_batch_record_current": [_vp, _i64, _i32, _vp, _i64, _vp, _sz],
         "rlb_batch_info": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_i64)],
         "rlb_batch_set_launch_shape": [_vp, _i32, _i32, _i32],
         "rlb_batch_get_launch_shape": [_vp, _P(_i32), _P(_i32), _P(_i32)],
@@ -548,6 +551,33 @@ class Batch:
 
     def sync(self):
         check(lib().rlb_batch_sync(self._h))
+
+    def record_current(self, steps, x, out=None, chunk=1024):
+        """`steps` batched steps; out[b, t] = j at column x of member b's
+        state before step t + 1 (x < 0 counts from each member's last
+        column: -2 is the column before the outlet).  out: a float64 device
+        tensor of shape (members, >= steps) with unit column stride; a new
+        (members, steps) tensor if None.  The row workspace holds `chunk`
+        steps."""
+        torch = _torch()
+        n = len(self.members)
+        if out is None:
+            out = torch.empty((n, steps), dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_cuda or out.dim() != 2 or out.shape[0] != n \
+                or out.shape[1] < steps or (steps > 1 and out.stride(1) != 1):
+            raise ValueError("out must be a float64 device tensor of shape (members, >= steps)")
+        nb = _sz()
+        check(lib().rlb_batch_record_workspace_bytes(self._h, int(max(1, min(chunk, steps, 32768))),
+                                                     ctypes.byref(nb)))
+        m = self.members[0]
+        with torch.cuda.stream(self.stream):
+            work = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        m._in(out)
+        check(lib().rlb_batch_record_current(self._h, int(steps), int(x), _vp(out.data_ptr()),
+                                              int(out.stride(0)) if steps else 0,
+                                              _vp(work.data_ptr()), nb.value))
+        m._out()
+        return out
 
     def info(self):
         c, cells, q, st = _i32(), _i64(), _i32(), _i64()

@@ -196,3 +196,118 @@ def test_member_cannot_step_alone():
     with pytest.raises(RLBError) as e:
         B[0].step(1)
     assert e.value.status == EINVAL
+
+
+REC_SIZES = [(96, 40), (130, 33), (64, 24)]
+REC_BORDERS = (0.06, 0.01, 0.12, 1.05)
+
+
+def rec_member(lat, b, nx, ny):
+    f = workloads.random_fields(nx, ny, seed=300 + b, beta=0.01)
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    lat.add_disks([(nx / 4.0, ny / 2.0 - 0.5, 4.5)])
+    return f
+
+
+@pytest.mark.parametrize("x,chunk", [(-2, 1024), (0, 7), (3, 1)])
+def test_batch_record_current(x, chunk):
+    """Open channels record in the step kernel: each member's series is
+    bitwise the series of the same channel recorded alone, in chunks of
+    1024, 7 and 1 steps (x < 0 counts from each member's outlet); it
+    equals the column-current kernel on the same states up to float32
+    sums in another order; the states match bitwise; member 0's series
+    follows the FP64 oracle (j scale: n_in * beta_in)."""
+    torch = need_gpu()
+    from oracle import diagnostics, geometry, rlb as orl
+    from paper_2205_04658_amd.rlb import Batch, Lattice
+    steps = 25
+    B = Batch(REC_SIZES, 0.7, open_x=True)
+    fs = [rec_member(B[b], b, nx, ny) for b, (nx, ny) in enumerate(REC_SIZES)]
+    B.set_open_borders(*REC_BORDERS)
+    B.step(3)
+    got = B.record_current(steps, x, chunk=chunk)
+    B.sync()
+    assert got.shape == (len(REC_SIZES), steps)
+    got = got.cpu()
+    scale = 0.12 * 0.06
+    for b, (nx, ny) in enumerate(REC_SIZES):
+        def alone():
+            lat = Lattice(nx, ny, 0.7, open_x=True)
+            rec_member(lat, b, nx, ny)
+            lat.set_open_borders(*REC_BORDERS)
+            lat.step(3)
+            return lat
+        lat = alone()
+        want = lat.record_current(steps, x % nx).cpu()
+        assert torch.equal(got[b], want), b
+        assert torch.equal(B[b].save_state().cpu(), lat.save_state().cpu()), b
+        lat = alone()
+        col = torch.zeros(steps, dtype=torch.float64, device="cuda")
+        for t in range(steps):
+            lat.column_current(x % nx, out=col[t:t + 1])
+            lat.step(1)
+        assert (got[b] - col.cpu()).abs().max().item() < 1e-7 * scale, b
+    nx, ny = REC_SIZES[0]
+    solid = geometry.disc_mask(nx, ny, [(nx / 4.0, ny / 2.0 - 0.5, 4.5)])
+    f = fs[0]
+    F, G = orl.initial_state(*(f[k].astype(np.float64) for k in ("eps", "bx", "by", "n")))
+    ref = []
+    for t in range(3 + steps):
+        if t >= 3:
+            ref.append(diagnostics.column_current(orl.fields(F, G, solid=solid), x % nx))
+        F, G = orl.step(F, G, 0.7, solid=solid, open_x=REC_BORDERS)
+    assert np.abs(got[0].numpy() - np.array(ref)).max() < 1e-5 * scale
+    assert np.ptp(ref) > 1e-3 * scale
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
+def test_batch_record_current_periodic(full):
+    """Periodic batches with walls, discs and a body force record with one
+    column launch before each step: bitwise the column kernel on each
+    member stepped alone, states bitwise equal."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Batch, Lattice
+    steps, x = 12, -5
+    B = Batch(SIZES, TAU, walls=True, full26=full)
+    for b, (nx, ny) in enumerate(SIZES):
+        setup_member(B[b], b, nx, ny)
+    B.set_body_force(*FB)
+    got = B.record_current(steps, x, chunk=5).cpu()
+    for b, (nx, ny) in enumerate(SIZES):
+        lat = Lattice(nx, ny, TAU, walls=True, full26=full)
+        setup_member(lat, b, nx, ny)
+        lat.set_body_force(*FB)
+        want = torch.zeros(steps, dtype=torch.float64, device="cuda")
+        for t in range(steps):
+            lat.column_current(nx + x, out=want[t:t + 1])
+            lat.step(1)
+        assert torch.equal(got[b], want.cpu()), b
+        assert torch.equal(B[b].save_state().cpu(), lat.save_state().cpu()), b
+        assert got[b].std().item() > 0.0
+
+
+def test_batch_record_current_errors_and_empty_runs():
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import EINVAL, EUNSUPPORTED, RLBError, Batch
+    B = Batch(REC_SIZES, 0.7, open_x=True)
+    for b, (nx, ny) in enumerate(REC_SIZES):
+        rec_member(B[b], b, nx, ny)
+    for x in (64, -65):                       # outside the 64-wide member
+        with pytest.raises(RLBError) as e:
+            B.record_current(2, x)
+        assert e.value.status == EINVAL
+    out = torch.empty((len(REC_SIZES), 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        B.record_current(5, -2, out=out)        # too short
+    assert B.record_current(0, -2).shape == (len(REC_SIZES), 0)
+    assert B.info()["step"] == 0
+    wide = torch.full((len(REC_SIZES), 10), -1.0, dtype=torch.float64, device="cuda")
+    B.record_current(4, 1, out=wide)            # row stride 10, first 4 columns written
+    B.sync()
+    w = wide.cpu()
+    assert bool((w[:, 4:] == -1.0).all()) and bool((w[:, :4] != -1.0).all())
+    assert B.info()["step"] == 4
+    C = Batch([(64, 8), (70, 8)], 0.7, cfl=1.25)
+    with pytest.raises(RLBError) as e:
+        C.record_current(2, 1)
+    assert e.value.status == EUNSUPPORTED
