@@ -63,7 +63,10 @@ typedef enum {
 
 /* Lattice parameters.
  *   nx, ny   lattice nodes (one z node); 4 <= nx, ny; ny * (nx rounded up
- *            to 64) < 2^30.
+ *            to 64) < 2^30, and one lattice row of state (nx rounded up to
+ *            64, times 4 bytes per plane, 2 x 17, 2 x 26 or 2 x 12 planes)
+ *            < 2^32 bytes: nx <= 31,580,608 folded, 20,648,832 with
+ *            RLB_FULL26, 44,739,200 with RLB_PLANAR.
  *   tau      relaxation time in time steps, tau > 1/2 (Ch. 3: eta =
  *            tau_R (eps + P) / 5; the scheme's shear viscosity is
  *            (tau - 1/2)/5 + nu_interp).

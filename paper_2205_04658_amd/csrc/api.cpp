@@ -53,6 +53,10 @@ struct StateHeader {
   uint32_t flags;
 };
 
+int planes_of(const rlb_params* p) {
+  return (p->flags & RLB_PLANAR) ? 12 : ((p->flags & RLB_FULL26) ? 26 : 17);
+}
+
 rlb_status check_params(const rlb_params* p) {
   if (!p) return fail(RLB_EINVAL, "params is null");
   if (p->nx < 4 || p->ny < 4) return fail(RLB_EINVAL, "nx, ny must be >= 4 (got %d x %d)", p->nx, p->ny);
@@ -72,6 +76,11 @@ rlb_status check_params(const rlb_params* p) {
     return fail(RLB_EUNSUPPORTED, "open x borders are implemented for the 3D momentum set");
   if (!std::isfinite(p->eps_ref) || !std::isfinite(p->n_ref))
     return fail(RLB_EINVAL, "eps_ref and n_ref must be finite");
+  // column offsets inside a state row are 32-bit byte offsets
+  const int64_t row_bytes = ((int64_t)p->nx + 63) / 64 * 64 * 2 * planes_of(p) * (int64_t)sizeof(float);
+  if (row_bytes >= (int64_t)1 << 32)
+    return fail(RLB_EINVAL, "a state row of nx = %d nodes takes %lld bytes, must be < 2^32", p->nx,
+                (long long)row_bytes);
   return RLB_OK;
 }
 
@@ -99,9 +108,6 @@ Workspace layout(const rlb_params* p, int Q, int64_t pitch) {
   return w;
 }
 
-int planes_of(const rlb_params* p) {
-  return (p->flags & RLB_PLANAR) ? 12 : ((p->flags & RLB_FULL26) ? 26 : 17);
-}
 
 // Bilinear tap weights per plane, quantised to multiples of 2^-24 with the
 // last weight taking the exact remainder, so the four float32 weights sum to
@@ -412,9 +418,13 @@ rlb_status rlb_set_body_force(rlb_lattice* lat, double fx, double fy) {
 rlb_status rlb_set_stirring(rlb_lattice* lat, double kmin, double kmax, double amplitude,
                             uint64_t seed) {
   if (rlb_status s = check_lat(lat)) return s;
-  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: use batches have no stirring");
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: batches have no stirring");
   if (lat->p.flags & RLB_PLANAR)
     return fail(RLB_EUNSUPPORTED, "the planar momentum set has no driving term");
+  // the twiddle table's items, (kMaxK + 1) * nx, are indexed with 32-bit
+  // integers (the row limit of check_params keeps the 3D sets below this)
+  if ((int64_t)(kMaxK + 1) * lat->p.nx >= ((int64_t)1 << 31))
+    return fail(RLB_EUNSUPPORTED, "stirring supports nx < %d", (int)(((int64_t)1 << 31) / (kMaxK + 1)));
   if (!std::isfinite(amplitude) || amplitude < 0.0) return fail(RLB_EINVAL, "amplitude must be finite and >= 0");
   if (amplitude == 0.0) {
     lat->stir = false;

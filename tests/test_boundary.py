@@ -50,12 +50,23 @@ def P(**kw):
     (dict(tau=0.5), B.EINVAL), (dict(tau=float("nan")), B.EINVAL),
     (dict(cfl=0.0), B.EINVAL), (dict(cfl=2.5), B.EUNSUPPORTED),
     (dict(cfl=1.25, flags=0x1), B.EUNSUPPORTED), (dict(cfl=1.25, flags=0x4), B.EUNSUPPORTED),
-    (dict(flags=0x10), B.EINVAL), (dict(eps_ref=float("inf")), B.EINVAL)])
+    (dict(flags=0x10), B.EINVAL), (dict(eps_ref=float("inf")), B.EINVAL),
+    (dict(nx=31580609, ny=4), B.EINVAL), (dict(nx=20648833, ny=4, flags=0x2), B.EINVAL),
+    (dict(nx=44739201, ny=4, flags=0x8), B.EINVAL)])
 def test_bad_params(L, kw, status):
     n = ctypes.c_size_t(123)
     assert L.rlb_workspace_bytes(ctypes.byref(P(**kw)), ctypes.byref(n)) == status
     assert n.value == 123            # nothing written on failure
     assert len(L.rlb_last_error()) > 0
+
+
+def test_widest_rows_are_accepted(L):
+    """The widest rows whose state still fits 32-bit column offsets (one
+    row of 2 x Q float32 planes, nx rounded up to 64, below 2^32 bytes)."""
+    n = ctypes.c_size_t()
+    for nx, flags, q in ((31580608, 0, 17), (20648832, 0x2, 26), (44739200, 0x8, 12)):
+        assert nx * 2 * q * 4 < 2 ** 32 <= (nx + 64) * 2 * q * 4
+        assert L.rlb_workspace_bytes(ctypes.byref(P(nx=nx, ny=4, flags=flags)), ctypes.byref(n)) == B.OK
 
 
 def test_wide_cfl_is_accepted_on_periodic_lattices(L):

@@ -11,7 +11,8 @@ after 200 steps, and members of the 64-channel batch.  The adjoint at
 512 x 256 over 2000 steps is checked through properties that hold at any
 size: its gradient along a random direction against a central difference
 of its own forward objective, and invariance under the checkpoint
-interval."""
+interval.  The widest rows the library accepts are sampled the same way
+(column offsets at the top of their 32-bit range)."""
 import numpy as np
 import pytest
 
@@ -133,6 +134,35 @@ def test_headline_step_sampled(start, full):
     ef, eg, change = sampled_step_error(lat, xs, ys, C["tau"], force, full, eps_ref, n_ref)
     assert ef < TOL and eg < TOL, (ef, eg)
     assert change > 10 * TOL          # the step moved the sampled populations
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
+def test_widest_rows_step_sampled(full):
+    """The widest rows the library accepts, 4 rows high (nx = 31,580,608
+    folded, 20,648,832 full set: one row of state just under 2^32 bytes,
+    so column offsets reach the top of their 32-bit range), forced by a
+    k-shell stirring: sampled one-step parity at both ends of the row,
+    around tile edges near the end, and in between."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    nx, ny = (20648832 if full else 31580608), 4
+    eps_ref, n_ref = 1.0, 0.1
+    lat = Lattice(nx, ny, 0.6, full26=full, eps_ref=eps_ref, n_ref=n_ref)
+    f = workloads.uniform(nx, ny, eps_ref, n_ref)
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    del f
+    stir = (0.5, 1.5, 2e-4, 11)          # |k| = 1 and sqrt(2) (kmax < ny / 2)
+    lat.set_stirring(*stir)
+    lat.set_launch_shape(*((4, 0, 16) if full else (2, 0, 16)))
+    t0 = 5
+    lat.step(t0)
+    xs = np.array([0, 1, 63, 64, 1000003, nx // 2 - 1, nx // 2, nx - 193, nx - 129, nx - 128,
+                   nx - 65, nx - 64, nx - 63, nx - 2, nx - 1, nx - 1])
+    ys = np.arange(len(xs)) % ny
+    force = forcing.Stirring(nx, ny, *stir).field_at(t0, xs, ys)
+    ef, eg, change = sampled_step_error(lat, xs, ys, 0.6, force, full, eps_ref, n_ref)
+    assert ef < TOL and eg < TOL, (ef, eg)
+    assert change > 10 * TOL
 
 
 def test_forced_1024_step_sampled_after_200_steps():
