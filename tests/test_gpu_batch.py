@@ -209,19 +209,21 @@ def rec_member(lat, b, nx, ny):
     return f
 
 
-@pytest.mark.parametrize("x,chunk", [(-2, 1024), (0, 7), (3, 1)])
-def test_batch_record_current(x, chunk):
+@pytest.mark.parametrize("x,chunk,full", [(-2, 1024, False), (0, 7, False), (3, 1, False),
+                                          (-2, 7, True)])
+def test_batch_record_current(x, chunk, full):
     """Open channels record in the step kernel: each member's series is
     bitwise the series of the same channel recorded alone, in chunks of
     1024, 7 and 1 steps (x < 0 counts from each member's outlet); it
     equals the column-current kernel on the same states up to float32
     sums in another order; the states match bitwise; member 0's series
-    follows the FP64 oracle (j scale: n_in * beta_in)."""
+    follows the FP64 oracle (j scale: n_in * beta_in); folded and full
+    sets."""
     torch = need_gpu()
     from oracle import diagnostics, geometry, rlb as orl
     from paper_2205_04658_amd.rlb import Batch, Lattice
     steps = 25
-    B = Batch(REC_SIZES, 0.7, open_x=True)
+    B = Batch(REC_SIZES, 0.7, open_x=True, full26=full)
     fs = [rec_member(B[b], b, nx, ny) for b, (nx, ny) in enumerate(REC_SIZES)]
     B.set_open_borders(*REC_BORDERS)
     B.step(3)
@@ -232,7 +234,7 @@ def test_batch_record_current(x, chunk):
     scale = 0.12 * 0.06
     for b, (nx, ny) in enumerate(REC_SIZES):
         def alone():
-            lat = Lattice(nx, ny, 0.7, open_x=True)
+            lat = Lattice(nx, ny, 0.7, open_x=True, full26=full)
             rec_member(lat, b, nx, ny)
             lat.set_open_borders(*REC_BORDERS)
             lat.step(3)
