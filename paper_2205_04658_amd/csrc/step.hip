@@ -126,8 +126,8 @@ __device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc&
   float Fsx = 0.0f, Fsy = 0.0f;   // stirring force, loaded with the populations
   if constexpr (FORCE == FORCE_STIR && MODE != MODE_FIELDS) {
     const gfloat* fr = (const gfloat*)L.force + (int64_t)y * row;
-    Fsx = fr[x];
-    Fsy = fr[L.pitch + x];
+    Fsx = __builtin_nontemporal_load(&fr[x]);   // read once: keep L2 for the state rows
+    Fsy = __builtin_nontemporal_load(&fr[L.pitch + x]);
   }
   // Solid nodes bounce back (F'_i = F~_opp(i)).  They run the same
   // arithmetic on a rest-frame stand-in and select at the store, so a
