@@ -118,18 +118,21 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   const Nbr nb = neighbourhood<Q>(x, y, a.nx, a.ny, a.row);
   const StepShared& sh = a.sh;
 
+  // The first adjoint step has no mu_{t+1}: its transposed pulls then read
+  // the state and are discarded by a select, so that all pulls stay one
+  // branch-free batch of loads (a branch per plane made the compiler wait
+  // for each plane's loads in turn).
+  const bool have_mu = a.mu_in != nullptr;
+  const float* mu = have_mu ? a.mu_in : a.state;
   float f[Q], g[Q], lf[Q], lg[Q];
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
     f[p] = pull<DS, UNIT, p, p, false>(a.state, nb, sh.tap[p]);
     g[p] = pull<DS, UNIT, p, Q + p, false>(a.state, nb, sh.tap[p]);
-    if (a.mu_in) {
-      lf[p] = pull<DS, UNIT, p, p, true>(a.mu_in, nb, sh.tap[p]);
-      lg[p] = pull<DS, UNIT, p, Q + p, true>(a.mu_in, nb, sh.tap[p]);
-    } else {
-      lf[p] = 0.0f;
-      lg[p] = 0.0f;
-    }
+    const float mf_in = pull<DS, UNIT, p, p, true>(mu, nb, sh.tap[p]);
+    const float mg_in = pull<DS, UNIT, p, Q + p, true>(mu, nb, sh.tap[p]);
+    lf[p] = have_mu ? mf_in : 0.0f;
+    lg[p] = have_mu ? mg_in : 0.0f;
   });
   // this node's force and accumulators, loaded with the populations so
   // that their latency overlaps the pulls (the accumulators would otherwise
