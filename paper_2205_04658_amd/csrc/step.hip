@@ -92,8 +92,8 @@ __device__ __forceinline__ void open_borders(const StepShared& a, int x, int nx,
   });
 }
 
-template <class DS, int SM, bool MASK, int FORCE, int MODE>
-__device__ __forceinline__ void node_update(const StepShared& sh, const LatDesc& L,
+template <class DS, int SM, bool MASK, int FORCE, int MODE, class Desc>
+__device__ __forceinline__ void node_update(const StepShared& sh, Desc& L,
                                             const float* __restrict__ src,
                                             float* __restrict__ dst,
                                             float* __restrict__ fields, int x, int y,
@@ -364,8 +364,13 @@ __global__ __launch_bounds__(64 * TY, DS::Q == 26 ? 3 : 1) void tile_kernel(cons
   const int row = threadIdx.x >> 6;
   for (int t = lo + (int)(blockIdx.x >> 3); t < hi; t += per) {
     const int tile = a.tile_first + t;
-    const int b = a.tile_lat ? a.tile_lat[tile] : 0;
-    const LatDesc& L = a.lats[b];
+    // the tile's lattice and its descriptor are wave-uniform and read-only
+    // here: read through the constant address space (scalar loads, which
+    // never wait on the vector-memory counter the pulls are counted on)
+    typedef const __attribute__((address_space(4))) int32_t CI32;
+    typedef const __attribute__((address_space(4))) LatDesc CDesc;
+    const int b = a.tile_lat ? ((CI32*)a.tile_lat)[tile] : 0;
+    CDesc& L = ((CDesc*)a.lats)[b];
     // tiles of a lattice run strip by strip (strips a.strip tiles wide,
     // the last one narrower), row-major inside a strip: neighbouring tiles,
     // which share halo rows and columns, are dispatched close together
