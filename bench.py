@@ -110,7 +110,8 @@ print(json.dumps(dict(steps=steps, seconds=el, cells=n * n)))
                       f"{d['steps']} steps in {d['seconds']:.1f} s, float64 NumPy, 1 thread"}
 
 
-def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=None, cfl=1.0):
+def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=None, cfl=1.0,
+              repeats=0):
     c = workloads.FORCED_4096
     nx, ny = c["nx"], c["ny"]
     planar = layout == "planar12"
@@ -143,6 +144,17 @@ def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=No
     lat.sync()
     q = lat.layout()[0]
     cells = nx * ny
+    # the spread of the same measurement: `repeats` more timed windows of
+    # min(steps, 1000) steps each, after the one that gives the result
+    windows = []
+    for _ in range(repeats):
+        n = min(steps, 1000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat.step(n)
+        torch.cuda.synchronize()
+        windows.append(cells * n / (time.perf_counter() - t1) / 1e6)
+    lat.sync()
     # algorithmic bytes of one step-kernel launch: every population plane
     # read once and written once (2 families x q planes x 4 B each way)
     # plus the two float32 stirring-force planes read
@@ -155,6 +167,10 @@ def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=No
                bytes_per_launch=bytes_per_launch, achieved_gbs=achieved,
                traffic=measured_traffic(layout), shape=lat.launch_shape(),
                tune=[list(r) for r in tune])
+    if windows:
+        w = sorted(windows)
+        out["repeats"] = dict(n=len(w), steps_each=min(steps, 1000), median_mlups=w[len(w) // 2],
+                              min_mlups=w[0], max_mlups=w[-1])
     del lat
     torch.cuda.empty_cache()
     return out
@@ -389,6 +405,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--layout", default="folded17", choices=["folded17", "full26"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="extra timed windows of the headline step, reported as their spread")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -404,7 +422,8 @@ def main():
     rlb.lib()
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
     shape = tuple(int(v) for v in a.shape.split(",")) if a.shape else None
-    main_run = run_plain(torch, rlb, workloads, a.layout, a.steps, a.warmup, shape)
+    main_run = run_plain(torch, rlb, workloads, a.layout, a.steps, a.warmup, shape,
+                         repeats=a.repeats)
     variants = {}
     if not a.no_variants:
         other = "full26" if a.layout == "folded17" else "folded17"
@@ -460,6 +479,7 @@ def main():
                      "unit": "GB/s", "frac": r["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": r["traffic"], "kernel_ms": r["kernel_ms"],
                      "bytes_per_cell": r["bytes_per_cell"], "bytes_per_launch": r["bytes_per_launch"]},
+        "repeats": r.get("repeats"),
         "copy_probe_gbs": copy_gbs,
         "batched": batched,
         "adjoint": adjoint,
