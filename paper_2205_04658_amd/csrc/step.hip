@@ -92,6 +92,17 @@ __device__ __forceinline__ void open_borders(const StepShared& a, int x, int nx,
   });
 }
 
+// Kernels whose waves raise their issue priority while they issue the pulls
+// (measured): the folded two-cell (cfl > 1) step at 4096^2 (+3%), the
+// open-channel steps (1024x256 channel +5..9%, six-channel batch +1%), and
+// the masked, stirred steps of the adjoint (forward 11.6k -> 13.0k MLUPS,
+// its objective steps included).  The cfl <= 1 step at 4096^2 loses 5%
+// with it and the masked batched step with a body force 0.7%.
+template <class DS, int SM, bool MASK, int FORCE, int MODE>
+constexpr bool kLoadPriority =
+    (MODE == MODE_STEP && SM == SM_WIDE && DS::Q == 17) || MODE == MODE_OPEN ||
+    MODE == MODE_OBJ || (MODE == MODE_STEP && MASK && FORCE == FORCE_STIR);
+
 template <class DS, int SM, bool MASK, int FORCE, int MODE, class Desc>
 __device__ __forceinline__ void node_update(const StepShared& sh, Desc& L,
                                             const float* __restrict__ src,
@@ -110,10 +121,8 @@ __device__ __forceinline__ void node_update(const StepShared& sh, Desc& L,
   const uint32_t node = (uint32_t)(y * nx + x);   // dense index (mask, fields)
   const StepShared& a = sh;
 
-  // 1. pull-stream every plane.  The folded two-cell (cfl > 1) step raises
-  // the wave's issue priority while it issues its loads (measured 3% at
-  // 4096^2; the same in the cfl <= 1 kernels costs 5%)
-  if constexpr (MODE == MODE_STEP && SM == SM_WIDE && DS::Q == 17) __builtin_amdgcn_s_setprio(2);
+  // 1. pull-stream every plane (at raised issue priority where that helps)
+  if constexpr (kLoadPriority<DS, SM, MASK, FORCE, MODE>) __builtin_amdgcn_s_setprio(2);
   float f[Q], g[Q];
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
@@ -132,7 +141,7 @@ __device__ __forceinline__ void node_update(const StepShared& sh, Desc& L,
     Fsx = __builtin_nontemporal_load(&fr[x]);   // read once: keep L2 for the state rows
     Fsy = __builtin_nontemporal_load(&fr[L.pitch + x]);
   }
-  if constexpr (MODE == MODE_STEP && SM == SM_WIDE && DS::Q == 17) __builtin_amdgcn_s_setprio(0);
+  if constexpr (kLoadPriority<DS, SM, MASK, FORCE, MODE>) __builtin_amdgcn_s_setprio(0);
   // Solid nodes bounce back (F'_i = F~_opp(i)).  They run the same
   // arithmetic on a rest-frame stand-in and select at the store, so a
   // wavefront that straddles an obstacle does not diverge.
