@@ -267,6 +267,19 @@ rlb_status rlb_record_workspace_bytes(const rlb_lattice* lat, int32_t chunk, siz
 rlb_status rlb_record_current(rlb_lattice* lat, int64_t nsteps, int32_t x, double* d_series,
                               void* d_work, size_t bytes);
 
+/* rlb_record_current without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid allocation): the per-row currents go to a fixed device scratch of
+ * 4 MiB inside the library (one per device, held until the process ends),
+ * so a chunk holds min(65536, 4 MiB / (8 ny)) steps.  Same steps, kernels
+ * and results as rlb_record_current (bitwise).  It calls no allocating
+ * routine.  RLB_ENOMEM when one step's rows do not fit (ny > 524288); other
+ * errors as rlb_record_current.  Every call on a device shares that
+ * device's scratch: calls that overlap on one device (two streams, two
+ * threads) race and must be serialised by the caller. */
+rlb_status rlb_record_current_noalloc(rlb_lattice* lat, int64_t nsteps, int32_t x,
+                                      double* d_series);
+
 /* One-sided power spectrum of the fluctuations of a float64 device series
  * s[0..n), 2 <= n <= 2^26: d_out[k] = |sum_t (s_t - mean) e^{-2 pi i k t/n}|^2
  * / n^2 for k = 0 .. n/2 (n/2 + 1 doubles; a plain sum, angles reduced

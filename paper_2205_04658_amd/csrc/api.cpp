@@ -679,20 +679,30 @@ rlb_status rlb_record_workspace_bytes(const rlb_lattice* lat, int32_t chunk, siz
   return RLB_OK;
 }
 
-rlb_status rlb_record_current(rlb_lattice* lat, int64_t nsteps, int32_t x, double* d_series,
-                              void* d_work, size_t bytes) {
+namespace {
+
+// Checks shared by rlb_record_current and rlb_record_current_noalloc
+// (everything but the workspace).  *done is set when there is nothing to do.
+rlb_status check_record(const rlb_lattice* lat, int64_t nsteps, int32_t x, const double* d_series,
+                        bool* done) {
   if (rlb_status s = check_lat(lat)) return s;
   if (nsteps < 0) return fail(RLB_EINVAL, "nsteps must be >= 0");
   if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: step it with rlb_batch_step");
   if (x < 0 || x >= lat->p.nx) return fail(RLB_EINVAL, "column %d outside [0, %d)", x, lat->p.nx);
   if (lat->p.cfl > 1.0) return fail(RLB_EUNSUPPORTED, "the column current supports cfl <= 1");
-  if (nsteps == 0) return RLB_OK;
+  *done = nsteps == 0;
+  if (*done) return RLB_OK;
   if (!d_series || !aligned(d_series, 8))
     return fail(RLB_EINVAL, "d_series must be an 8-byte aligned device pointer");
-  if (!d_work || !aligned(d_work, 256)) return fail(RLB_EINVAL, "workspace must be a 256-byte aligned device pointer");
-  const size_t row_bytes = (size_t)lat->p.ny * sizeof(double);
-  const int64_t chunk = (int64_t)std::min<size_t>(bytes / row_bytes, 65536);
-  if (chunk < 1) return fail(RLB_ENOMEM, "record workspace has %zu bytes, needs at least %zu", bytes, row_bytes);
+  return RLB_OK;
+}
+
+// The recording steps, with `rows` (chunk * ny float64) holding the per-row
+// currents of up to `chunk` steps.  Every row of a recorded step is written
+// by the step kernel before the row means read it, so `rows` needs no
+// clearing.
+rlb_status record_steps(rlb_lattice* lat, int64_t nsteps, int32_t x, double* d_series, double* rows,
+                        int64_t chunk) {
   const int force = force_mode(lat);
   const StirArgs sa = stir_args(lat);
   if (!records_current(lat)) {   // record with the column kernel before each step
@@ -702,7 +712,6 @@ rlb_status rlb_record_current(rlb_lattice* lat, int64_t nsteps, int32_t x, doubl
     }
     return RLB_OK;
   }
-  double* rows = (double*)d_work;
   for (int64_t t0 = 0; t0 < nsteps; t0 += chunk) {
     const int64_t cnt = std::min(chunk, nsteps - t0);
     for (int64_t i = 0; i < cnt; ++i)
@@ -710,6 +719,35 @@ rlb_status rlb_record_current(rlb_lattice* lat, int64_t nsteps, int32_t x, doubl
     HIP_TRY(launch_row_means(rows, lat->p.ny, (int)cnt, d_series + t0, lat->stream), "row means");
   }
   return RLB_OK;
+}
+
+}  // namespace
+
+rlb_status rlb_record_current(rlb_lattice* lat, int64_t nsteps, int32_t x, double* d_series,
+                              void* d_work, size_t bytes) {
+  bool done = false;
+  if (rlb_status s = check_record(lat, nsteps, x, d_series, &done)) return s;
+  if (done) return RLB_OK;
+  if (!d_work || !aligned(d_work, 256)) return fail(RLB_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  const size_t row_bytes = (size_t)lat->p.ny * sizeof(double);
+  const int64_t chunk = (int64_t)std::min<size_t>(bytes / row_bytes, 65536);
+  if (chunk < 1) return fail(RLB_ENOMEM, "record workspace has %zu bytes, needs at least %zu", bytes, row_bytes);
+  return record_steps(lat, nsteps, x, d_series, (double*)d_work, chunk);
+}
+
+rlb_status rlb_record_current_noalloc(rlb_lattice* lat, int64_t nsteps, int32_t x, double* d_series) {
+  bool done = false;
+  if (rlb_status s = check_record(lat, nsteps, x, d_series, &done)) return s;
+  if (done) return RLB_OK;
+  const size_t row_bytes = (size_t)lat->p.ny * sizeof(double);
+  if (row_bytes > kStaticScratchBytes)
+    return fail(RLB_ENOMEM, "ny = %d rows need %zu bytes per step; the fixed scratch holds %zu "
+                "(ny <= %zu)", lat->p.ny, row_bytes, kStaticScratchBytes,
+                kStaticScratchBytes / sizeof(double));
+  double* rows = nullptr;
+  HIP_TRY(static_scratch(lat->device, &rows), "fixed scratch address");
+  const int64_t chunk = (int64_t)std::min<size_t>(kStaticScratchBytes / row_bytes, 65536);
+  return record_steps(lat, nsteps, x, d_series, rows, chunk);
 }
 
 rlb_status rlb_power_spectrum(const double* d_series, int64_t n, double* d_out, void* hip_stream) {

@@ -20,6 +20,8 @@ constexpr int kTileY = 4;            // four wavefronts per workgroup
 constexpr int kBlock = kTileX * kTileY;
 constexpr int kRedBlocks = 1024;     // partial sums of the totals kernel
 constexpr size_t kAlign = 256;
+// Size of the fixed device scratch of rlb_record_current_noalloc (noalloc.hip).
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
 
 // Device error bits (sticky word in the workspace).
 enum : uint32_t { ERR_LANDAU = 1u, ERR_NONFINITE = 2u };
@@ -302,6 +304,10 @@ hipError_t launch_grad_reduce(const double2* acc_f, const double* acc_itau, cons
 hipError_t launch_sum_rows(const double* partial, int cols, int rows, double scale, double* out,
                            hipStream_t s);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s);
+
+// noalloc.hip: device address of the fixed scratch (kStaticScratchBytes) on
+// `device`, looked up on first use with that device current.
+hipError_t static_scratch(int device, double** ptr);
 
 // reduce.hip
 hipError_t launch_totals(const rlb_lattice* lat, const float* state,

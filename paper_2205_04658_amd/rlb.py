@@ -37,7 +37,8 @@ SYMBOLS = [
     "rlb_batch_set_launch_shape", "rlb_batch_get_launch_shape", "rlb_batch_autotune",
     "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
     "rlb_set_relaxation_time", "rlb_set_relaxation_eta_s", "rlb_adjoint_workspace_bytes",
-    "rlb_adjoint_run", "rlb_set_open_borders", "rlb_column_current", "rlb_record_workspace_bytes", "rlb_record_current", "rlb_power_spectrum",
+    "rlb_adjoint_run", "rlb_set_open_borders", "rlb_column_current", "rlb_record_workspace_bytes", "rlb_record_current",
+    "rlb_record_current_noalloc", "rlb_power_spectrum",
     "rlb_spectrum_workspace_bytes", "rlb_energy_spectrum", "rlb_spectrum_average",
     "rlb_power_law_fit",
 ]
@@ -137,6 +138,7 @@ def lib():
         "rlb_column_current": [_vp, _i32, _vp],
         "rlb_record_workspace_bytes": [_vp, _i32, _P(_sz)],
         "rlb_record_current": [_vp, _i64, _i32, _vp, _vp, _sz],
+        "rlb_record_current_noalloc": [_vp, _i64, _i32, _vp],
         "rlb_power_spectrum": [_vp, _i64, _vp, _vp],
         "rlb_spectrum_workspace_bytes": [_vp, _i32, _P(_sz)],
         "rlb_energy_spectrum": [_vp, _i32, _d, _vp, _vp, _vp, _sz],
@@ -438,6 +440,20 @@ class Lattice:
         self._in(out, work)
         check(lib().rlb_record_current(self._h, int(steps), int(x), _vp(out.data_ptr()),
                                        _vp(work.data_ptr()), n.value))
+        self._out()
+        return out
+
+    def record_current_noalloc(self, steps, x, out=None):
+        """As record_current, through rlb_record_current_noalloc: the rows
+        go to the library's fixed device scratch instead of a workspace."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(steps, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < steps \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of >= steps elements")
+        self._in(out)
+        check(lib().rlb_record_current_noalloc(self._h, int(steps), int(x), _vp(out.data_ptr())))
         self._out()
         return out
 
