@@ -521,6 +521,34 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
 /* A plain device copy of `bytes` (multiple of 16) for bandwidth calibration. */
 rlb_status rlb_copy_probe(const void* d_src, void* d_dst, size_t bytes,
                           void* hip_stream);
+/* The two linear maps one reverse step of rlb_adjoint_run applies, on caller
+ * buffers, for checking them by the dot-product identity
+ * <A^T mu, v> = <mu, A v> against a tangent of the forward step:
+ *   RLB_ADJ_PULL_T  d_out = P^T d_mu, P the bilinear pull of the streaming
+ *                   step (Ch. 3, linear interpolation): the same weights
+ *                   taken at x + delta;
+ *   RLB_ADJ_STEP    d_out = (dC/dF~)^T P^T d_mu with F~ = P d_state: the
+ *                   adjoint kernel of one step (C the local update: moments,
+ *                   Landau matching, equilibrium, relaxation, the driving
+ *                   term of Ch. 4 eq. forceTerm with the lattice's body
+ *                   force and no stirring, bounce-back at the lattice's
+ *                   obstacles) with no objective term; d_acc (float64,
+ *                   3 nx ny) receives per node the adjoints with respect to
+ *                   the force at the node and 1/tau: (d/dF^x, d/dF^y) pairs
+ *                   at d_acc[2 (y nx + x)], d/d(1/tau) at
+ *                   d_acc[2 nx ny + y nx + x].
+ * d_state, d_mu, d_out: population copies in the lattice's layout
+ * (rlb_layout: 2 * planes planes of node bricks, row_stride * ny floats, no
+ * header; shifted storage for d_state).  All pointers 256-byte aligned;
+ * d_out must not alias an input.  RLB_ADJ_STEP overwrites the lattice's
+ * stirring-force planes (as rlb_adjoint_run does).  Asynchronous on the
+ * lattice stream.  Errors as rlb_adjoint_run for the lattice (constant tau,
+ * periodic x, cfl <= 1, 3D set); RLB_EINVAL for an unknown op or a bad
+ * pointer. */
+enum { RLB_ADJ_STEP = 0, RLB_ADJ_PULL_T = 1 };
+rlb_status rlb_adjoint_apply(rlb_lattice* lat, int32_t op, const float* d_state,
+                             const float* d_mu, float* d_out, double* d_acc);
+
 
 /* Human-readable message of the last failure on this thread. */
 const char* rlb_last_error(void);

@@ -54,18 +54,25 @@ def node_objective(F, G, kind, solid=None, cfl=1.0):
     return j[fluid].mean()
 
 
-def run_objective(fields, nsteps, tau, body, modes, amps, kind, solid=None, cfl=1.0):
-    """J(theta): initialise from float32 fields, take nsteps steps with the
-    basis-driven force and average the objective over steps N/2+1..N."""
+def run_objectives(fields, nsteps, tau, body, modes, amps, kinds, solid=None, cfl=1.0):
+    """J(theta) for each objective in `kinds` from one run: initialise from
+    float32 fields, take nsteps steps with the basis-driven force and
+    average each objective over steps N/2+1..N."""
     ny, nx = fields["eps"].shape
     F, G = rlb.initial_state(*(fields[k].astype(np.float64) for k in ("eps", "bx", "by", "n")))
     force = basis_force(nx, ny, modes, amps, body)
-    acc = 0.0
+    acc = np.zeros(len(kinds))
     for t in range(nsteps):
         F, G = rlb.step(F, G, tau, cfl=cfl, force=force, solid=solid)
         if t + 1 > nsteps // 2:
-            acc += node_objective(F, G, kind, solid, cfl)
+            for j, kind in enumerate(kinds):
+                acc[j] += node_objective(F, G, kind, solid, cfl)
     return acc / (nsteps - nsteps // 2)
+
+
+def run_objective(fields, nsteps, tau, body, modes, amps, kind, solid=None, cfl=1.0):
+    """J(theta) of one objective (see run_objectives)."""
+    return float(run_objectives(fields, nsteps, tau, body, modes, amps, (kind,), solid, cfl)[0])
 
 
 def fd_gradient(fields, nsteps, tau, body, modes, amps, kind, solid=None, rel=1e-4, which=None):

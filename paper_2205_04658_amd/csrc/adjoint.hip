@@ -327,6 +327,30 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   a.acc_itau[node] = at + (double)litau;
 }
 
+// The transposed bilinear pull alone, out = P^T mu: the pull of the
+// adjoint kernel (same weights taken at x + delta) without the local
+// reverse sweep, for checking <P^T mu, v> = <mu, P v>.
+template <class DS, bool UNIT>
+__global__ __launch_bounds__(256) void transpose_pull_kernel(const float* __restrict__ mu,
+                                                             float* __restrict__ out, int nx,
+                                                             int ny, int row, int tiles_x,
+                                                             int ntiles, const StepShared sh) {
+  constexpr int Q = DS::Q;
+  const int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  const int ty = tile / tiles_x;
+  const int x = (tile - ty * tiles_x) * 64 + (threadIdx.x & 63);
+  const int y = ty * 4 + (threadIdx.x >> 6);
+  if (x >= nx || y >= ny) return;
+  const Nbr nb = neighbourhood<Q>(x, y, nx, ny, row);
+  char* o = (char*)out + nb.r[1] + nb.c[1];
+  static_for<0, Q>([&](auto P) {
+    constexpr int p = decltype(P)::value;
+    *(float*)(o + p * 256) = pull<DS, UNIT, p, p, true>(mu, nb, sh.tap[p]);
+    *(float*)(o + (Q + p) * 256) = pull<DS, UNIT, p, Q + p, true>(mu, nb, sh.tap[p]);
+  });
+}
+
 // Objective density summed over fluid nodes, added to a per-block running
 // sum (fixed grid and order: deterministic).
 template <class DS, bool UNIT, bool MASK>
@@ -463,6 +487,26 @@ hipError_t launch_adjoint(int Q, bool unit, bool mask, const AdjArgs& a, hipStre
     if (unit) adj_go<Dir17, true>(mask, a, s); else adj_go<Dir17, false>(mask, a, s);
   } else {
     if (unit) adj_go<Dir26, true>(mask, a, s); else adj_go<Dir26, false>(mask, a, s);
+  }
+  return hipGetLastError();
+}
+
+template <class DS, bool UNIT>
+static void tpull_go(const float* mu, float* out, int nx, int ny, int row, const StepShared& sh,
+                     hipStream_t s) {
+  const int tiles_x = (nx + 63) / 64, ntiles = tiles_x * ((ny + 3) / 4);
+  hipLaunchKernelGGL((transpose_pull_kernel<DS, UNIT>), dim3(ntiles), dim3(256), 0, s, mu, out, nx,
+                     ny, row, tiles_x, ntiles, sh);
+}
+
+hipError_t launch_transpose_pull(int Q, bool unit, const float* mu, float* out, int nx, int ny,
+                                 int row, const StepShared& sh, hipStream_t s) {
+  if (Q == 17) {
+    if (unit) tpull_go<Dir17, true>(mu, out, nx, ny, row, sh, s);
+    else tpull_go<Dir17, false>(mu, out, nx, ny, row, sh, s);
+  } else {
+    if (unit) tpull_go<Dir26, true>(mu, out, nx, ny, row, sh, s);
+    else tpull_go<Dir26, false>(mu, out, nx, ny, row, sh, s);
   }
   return hipGetLastError();
 }

@@ -49,15 +49,22 @@ struct AdjLayout {
   int64_t nseg, nbuf;
 };
 
-rlb_status check_cfg(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
+// Lattice settings the adjoint differentiates (shared by rlb_adjoint_run
+// and rlb_adjoint_apply).
+rlb_status check_adjoint_lattice(const rlb_lattice* lat) {
   if (!lat) return afail(RLB_EINVAL, "lattice is null");
-  if (!c) return afail(RLB_EINVAL, "config is null");
   if (lat->tau_k > 0.0)
     return afail(RLB_EUNSUPPORTED, "the adjoint needs a constant relaxation time (rlb_set_relaxation_time)");
   if (lat->p.flags & RLB_OPEN_X)
     return afail(RLB_EUNSUPPORTED, "the adjoint supports periodic x borders only");
   if (lat->p.cfl > 1.0) return afail(RLB_EUNSUPPORTED, "the adjoint supports cfl <= 1 only");
   if (lat->p.flags & RLB_PLANAR) return afail(RLB_EUNSUPPORTED, "the adjoint supports the 3D momentum set only");
+  return RLB_OK;
+}
+
+rlb_status check_cfg(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
+  if (rlb_status s = check_adjoint_lattice(lat)) return s;
+  if (!c) return afail(RLB_EINVAL, "config is null");
   if (c->nsteps < 2 || (c->nsteps & 1)) return afail(RLB_EINVAL, "nsteps must be even and >= 2");
   if (c->checkpoint < 1) return afail(RLB_EINVAL, "checkpoint interval must be >= 1");
   if (c->objective != RLB_OBJ_CURRENT && c->objective != RLB_OBJ_DISSIPATION)
@@ -331,6 +338,47 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
   AHIP(hipMemcpyAsync(&h, lat->err, sizeof h, hipMemcpyDeviceToHost, st), "read error flag");
   AHIP(hipStreamSynchronize(st), "stream synchronize");
   if (h & ERR_LANDAU) return afail(RLB_ELANDAU, "a fluid node had no timelike Landau frame");
+  return RLB_OK;
+}
+
+rlb_status rlb_adjoint_apply(rlb_lattice* lat, int32_t op, const float* d_state, const float* d_mu,
+                             float* d_out, double* d_acc) {
+  if (rlb_status s = check_adjoint_lattice(lat)) return s;
+  if (op != RLB_ADJ_STEP && op != RLB_ADJ_PULL_T) return afail(RLB_EINVAL, "unknown operation %d", op);
+  auto ok = [](const void* p) { return p && ((uintptr_t)p % kAlign) == 0; };
+  if (!ok(d_mu) || !ok(d_out)) return afail(RLB_EINVAL, "d_mu and d_out must be 256-byte aligned device pointers");
+  if ((const void*)d_out == (const void*)d_mu || (const void*)d_out == (const void*)d_state)
+    return afail(RLB_EINVAL, "d_out must not alias the inputs");
+  const bool unit = lat->p.cfl == 1.0;
+  if (op == RLB_ADJ_PULL_T) {
+    AHIP(launch_transpose_pull(lat->Q, unit, d_mu, d_out, lat->p.nx, lat->p.ny, lat->row,
+                               shared_of(lat), lat->stream), "transposed pull");
+    return RLB_OK;
+  }
+  if (!ok(d_state) || !ok(d_acc))
+    return afail(RLB_EINVAL, "d_state and d_acc must be 256-byte aligned device pointers");
+  const size_t ncell = (size_t)lat->p.nx * lat->p.ny;
+  // no stirring: the force planes the adjoint kernel adds to the body force are zero
+  AHIP(launch_zero_f64((double*)lat->desc.force, (size_t)lat->pitch, lat->stream), "zero force");
+  AHIP(launch_zero_f64(d_acc, 3 * ncell, lat->stream), "zero accumulators");
+  AdjArgs aa;
+  aa.sh = shared_of(lat);
+  aa.state = d_state;
+  aa.mu_in = d_mu;
+  aa.mu_out = d_out;
+  aa.mask = lat->any_solid ? lat->mask : nullptr;
+  aa.force = lat->desc.force;
+  aa.acc_f = (double2*)d_acc;
+  aa.acc_itau = d_acc + 2 * ncell;
+  aa.pitch = lat->pitch;
+  aa.nx = lat->p.nx;
+  aa.ny = lat->p.ny;
+  aa.row = lat->row;
+  aa.tiles_x = (lat->p.nx + 63) / 64;
+  aa.ntiles = aa.tiles_x * ((lat->p.ny + 3) / 4);
+  aa.obj_c = 0.0f;
+  aa.kind = 0;
+  AHIP(launch_adjoint(lat->Q, unit, lat->any_solid, aa, lat->stream), "adjoint");
   return RLB_OK;
 }
 

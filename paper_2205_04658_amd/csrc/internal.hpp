@@ -299,6 +299,9 @@ hipError_t launch_objective(int Q, bool unit, bool mask, const ObjArgs& a, int g
 hipError_t launch_basis_force(const double* modes, const double* amps, int M, int nx, int ny,
                               int row, int64_t pitch, float* force, hipStream_t s);
 hipError_t launch_grad_reduce(const double2* acc_f, const double* acc_itau, const double* modes,
+// out = P^T mu (the adjoint kernel's transposed pull alone)
+hipError_t launch_transpose_pull(int Q, bool unit, const float* mu, float* out, int nx, int ny,
+                                 int row, const StepShared& sh, hipStream_t s);
                               int M, int nx, int ny, double tau, double* partial, int cols,
                               double* out, hipStream_t s);
 hipError_t launch_sum_rows(const double* partial, int cols, int rows, double scale, double* out,

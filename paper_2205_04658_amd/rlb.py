@@ -37,7 +37,7 @@ SYMBOLS = [
     "rlb_batch_set_launch_shape", "rlb_batch_get_launch_shape", "rlb_batch_autotune",
     "rlb_batch_use_graph", "rlb_batch_timing", "rlb_batch_timing_read",
     "rlb_set_relaxation_time", "rlb_set_relaxation_eta_s", "rlb_adjoint_workspace_bytes",
-    "rlb_adjoint_run", "rlb_set_open_borders", "rlb_column_current", "rlb_record_workspace_bytes", "rlb_record_current",
+    "rlb_adjoint_run", "rlb_adjoint_apply", "rlb_set_open_borders", "rlb_column_current", "rlb_record_workspace_bytes", "rlb_record_current",
     "rlb_record_current_noalloc", "rlb_power_spectrum",
     "rlb_spectrum_workspace_bytes", "rlb_energy_spectrum", "rlb_spectrum_average",
     "rlb_power_law_fit",
@@ -146,6 +146,7 @@ def lib():
         "rlb_power_law_fit": [_vp, _vp, _i32, _P(_d), _P(_d)],
         "rlb_adjoint_workspace_bytes": [_vp, _P(AdjointCfg), _P(_sz)],
         "rlb_adjoint_run": [_vp, _P(AdjointCfg), _vp, _sz, _P(_d), _vp],
+        "rlb_adjoint_apply": [_vp, _i32, _vp, _vp, _vp, _vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -363,6 +364,48 @@ class Lattice:
         f = f.view(self.ny, row // 64, 2 * q, 64).permute(2, 0, 1, 3).reshape(2 * q, self.ny, row)
         f = f[:, :, :self.nx]
         return f[:q], f[q:]
+
+    def bricks(self, planes):
+        """A population copy in the lattice's node-brick layout (rlb_layout)
+        from planes of shape (2Q, ny, nx): a float32 device tensor of
+        row_stride * ny elements, padding columns zero."""
+        torch = _torch()
+        q, row, stride, _ = self.layout()
+        planes = planes.to(device=self.device, dtype=torch.float32)
+        if tuple(planes.shape) != (2 * q, self.ny, self.nx):
+            raise ValueError(f"planes must have shape {(2 * q, self.ny, self.nx)}")
+        full = torch.zeros((2 * q, self.ny, row), dtype=torch.float32, device=self.device)
+        full[:, :, :self.nx] = planes
+        return full.view(2 * q, self.ny, row // 64, 64).permute(1, 2, 0, 3).contiguous().view(-1)
+
+    def unbricks(self, buf):
+        """Inverse of bricks: (2Q, ny, nx) planes of a node-brick copy."""
+        q, row, stride, _ = self.layout()
+        f = buf[:self.ny * stride].view(self.ny, row // 64, 2 * q, 64).permute(2, 0, 1, 3)
+        return f.reshape(2 * q, self.ny, row)[:, :, :self.nx]
+
+    def adjoint_apply(self, op, mu, state=None):
+        """rlb_adjoint_apply on planes of shape (2Q, ny, nx): op "pull_t"
+        returns P^T mu; op "step" returns ((dC/dF~)^T P^T mu at the given
+        shifted state, per-node adjoints (ny, nx, 3) of (F^x, F^y, 1/tau))."""
+        torch = _torch()
+        code = {"step": 0, "pull_t": 1}[op]
+        m = self.bricks(mu)
+        out = torch.zeros_like(m)
+        st = self.bricks(state) if code == 0 else None
+        acc = torch.zeros(3 * self.nx * self.ny + 32, dtype=torch.float64, device=self.device) \
+            if code == 0 else None
+        self._in(*(t for t in (m, out, st, acc) if t is not None))
+        check(lib().rlb_adjoint_apply(self._h, code, _vp(st.data_ptr()) if st is not None else None,
+                                      _vp(m.data_ptr()), _vp(out.data_ptr()),
+                                      _vp(acc.data_ptr()) if acc is not None else None))
+        self._out()
+        res = self.unbricks(out)
+        if code == 1:
+            return res
+        n = self.nx * self.ny
+        a = torch.stack([acc[0:2 * n:2], acc[1:2 * n:2], acc[2 * n:3 * n]], 1).view(self.ny, self.nx, 3)
+        return res, a
 
     def stirring_coefficients(self, step):
         torch = _torch()

@@ -76,6 +76,34 @@ def _full_dirs():
     return d + [(vx, vy, -vz) for vx, vy, vz in d[8:]]
 
 
+def _dir_index(vx, vy, vz):
+    return int(np.argmin(np.abs(rlb.V - np.array([vx, vy, vz])).sum(axis=1)))
+
+
+def expand(P, full):
+    """Library planes (Q, ...) of one family -> the oracle's 26 populations:
+    the full set's planes reordered, or each folded plane split evenly over
+    its z-mirror pair (the states the folded layout represents are
+    z-symmetric)."""
+    out = np.zeros((26,) + P.shape[1:])
+    if full:
+        for k, d in enumerate(_full_dirs()):
+            out[_dir_index(*d)] = P[k]
+    else:
+        for k, (vx, vy, az) in enumerate(_folded_dirs()):
+            idx = [i for i in range(26) if np.allclose(rlb.V[i, :2], (vx, vy)) and
+                   np.isclose(abs(rlb.V[i, 2]), az)]
+            for i in idx:
+                out[i] = P[k] / len(idx)
+    return out
+
+
+def contract(F, full):
+    """Oracle 26 populations -> library planes of one family (inverse of
+    expand on z-symmetric populations)."""
+    return unfold26(F) if full else fold(F)
+
+
 def compare(gpu, ora, sc, names=None):
     """Max scaled error per field (gpu: dict of tensors, ora: dict of arrays)."""
     names = names or list(gpu)

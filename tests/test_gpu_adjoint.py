@@ -1,12 +1,20 @@
 """Adjoint of the step: gradients of time-averaged channel objectives with
 respect to (F_b, tau, A_1..A_M) against central finite differences of the
-FP64 oracle, checkpoint-interval invariance, and the autograd wrapper."""
+FP64 oracle (a short run computed here, and the 200-step, 32-mode instance
+stored by tests/golden/make_golden.py), the dot-product identity of the
+adjoint kernel and of the transposed pull against tangents of the FP64
+step, checkpoint-interval invariance, and the autograd wrapper."""
+import json
+import os
+
 import numpy as np
 import pytest
 
-from oracle import geometry, objective
+from oracle import geometry, objective, rlb
 from paper_2205_04658_amd import workloads
-from rlbtest import need_gpu
+from rlbtest import contract, expand, need_gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint64_oracle.json")
 
 pytestmark = pytest.mark.gpu
 
@@ -104,3 +112,169 @@ def test_eta_s_relaxation_is_rejected_by_the_adjoint():
             call()
         assert e.value.status == EINVAL
     B.close()
+
+
+# ---------------------------------------------------------------------------
+# 64 x 32 channel, 200 steps, all 32 basis modes, both objectives, against
+# the stored FP64 oracle finite differences (relative step 1e-4)
+# ---------------------------------------------------------------------------
+GOLD = json.load(open(GOLDEN))
+# parameter groups, each judged on its own scale: the body force, the
+# relaxation time, the 32 stirring amplitudes
+GROUPS = {"F_b": [0], "tau": [1], "A": list(range(2, 2 + GOLD["config"]["nmodes"]))}
+
+
+def golden_run(kind, K):
+    from paper_2205_04658_amd.rlb import Lattice
+    c = GOLD["config"]
+    lat = Lattice(c["nx"], c["ny"], c["tau"], walls=True, eps_ref=c["eps"], n_ref=c["n"])
+    f = workloads.uniform(c["nx"], c["ny"], c["eps"], c["n"])
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    lat.add_disks(np.array(c["discs"], np.float64))
+    modes = workloads.stirring_basis(c["nx"], c["ny"], c["nmodes"], c["kmin"], c["kmax"],
+                                     c["basis_seed"])
+    amps = np.full(c["nmodes"], c["mode_amplitude"])
+    return lat.adjoint_run(c["steps"], K, kind, modes, amps, c["body_force"])
+
+
+@pytest.mark.parametrize("kind", ["current", "dissipation"])
+def test_gradient_every_component_vs_stored_oracle(kind):
+    """Every component of dJ/d(F_b, tau, A_1..A_32) within 1e-3 relative of
+    the FP64 oracle's central difference wherever it exceeds 1e-3 of the
+    largest component of its group; dJ/dtau always relative."""
+    need_gpu()
+    ref = GOLD[kind]
+    fd = np.array(ref["fd_grad"])
+    J, g = golden_run(kind, K=50)
+    print(f"{kind}: J gpu {J:.9e} oracle {ref['J']:.9e}")
+    assert abs(J - ref["J"]) <= 1e-5 * abs(ref["J"]), (J, ref["J"])
+    worst = {}
+    for name, idx in GROUPS.items():
+        scale = np.abs(fd[idx]).max()
+        for i in idx:
+            rel = abs(g[i] - fd[i]) / abs(fd[i])
+            if name == "tau" or abs(fd[i]) > 1e-3 * scale:
+                worst[name] = max(worst.get(name, 0.0), rel)
+                assert rel < 1e-3, (kind, GOLD["params"][i], g[i], fd[i], rel)
+            else:
+                assert abs(g[i] - fd[i]) < 1e-6 * scale, (kind, GOLD["params"][i], g[i], fd[i])
+    print(f"{kind}: worst relative error per group {worst}")
+
+
+# ---------------------------------------------------------------------------
+# Dot-product identities of the two linear maps one reverse step applies
+# ---------------------------------------------------------------------------
+def _family_maps(full, Q):
+    """Library planes (2Q, ny, nx) <-> the oracle's (F, G) populations."""
+    def to_pop(x):
+        return expand(x[:Q], full), expand(x[Q:], full)
+
+    def to_planes(F, G):
+        return np.concatenate([contract(F, full), contract(G, full)])
+    return to_pop, to_planes
+
+
+def _pull(x, full, Q, cfl):
+    to_pop, to_planes = _family_maps(full, Q)
+    F, G = to_pop(x)
+    return to_planes(rlb.stream(F, cfl), rlb.stream(G, cfl))
+
+
+@pytest.mark.parametrize("cfl", [1.0, 0.5])
+@pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
+def test_transposed_pull_dot_product(full, cfl):
+    """<P^T mu, v> = <mu, P v>: the adjoint's transposed pull on the GPU
+    against the oracle's bilinear pull, on a 67 x 37 lattice (ragged tiles,
+    periodic wrap)."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    nx, ny = 67, 37
+    lat = Lattice(nx, ny, 0.8, cfl=cfl, full26=full)
+    Q = lat.layout()[0]
+    rng = np.random.default_rng(11)
+    mu = rng.standard_normal((2 * Q, ny, nx)).astype(np.float32)
+    v = rng.standard_normal((2 * Q, ny, nx))
+    pt = lat.adjoint_apply("pull_t", torch.from_numpy(mu)).double().cpu().numpy()
+    terms = pt * v
+    lhs = terms.sum()
+    rhs = (mu.astype(np.float64) * _pull(v, full, Q, cfl)).sum()
+    err = abs(lhs - rhs) / np.abs(terms).sum()
+    print(f"transposed pull: <P^T mu, v> {lhs:.9e}  <mu, P v> {rhs:.9e}  rel {err:.2e}")
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
+def test_adjoint_step_dot_product(full):
+    """One adjoint kernel step (no objective term) on a developed channel
+    state: <(dC/dF~)^T P^T mu, P v> = <mu, P S'(s) v> with S'(s) v the
+    central difference of the FP64 step, and the kernel's per-node force
+    and 1/tau adjoints against the derivatives of the FP64 step with
+    respect to a random force field and to tau."""
+    torch = need_gpu()
+    lat = gpu_lattice() if not full else None
+    if full:
+        from paper_2205_04658_amd.rlb import Lattice
+        lat = Lattice(NX, NY, TAU, walls=True, full26=True)
+        f = fields()
+        lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        lat.add_disks(DISCS)
+    lat.set_body_force(FB, 0.0)
+    lat.step(25)
+    Q = lat.layout()[0]
+    pf, pg = lat.planes()
+    s32 = torch.cat([pf, pg]).cpu().numpy()
+    rng = np.random.default_rng(4)
+    mu = rng.standard_normal(s32.shape).astype(np.float32)
+    out, acc = lat.adjoint_apply("step", torch.from_numpy(mu), torch.from_numpy(s32))
+    lat.sync()
+    out = out.double().cpu().numpy()
+    acc = acc.cpu().numpy()
+
+    to_pop, to_planes = _family_maps(full, Q)
+    w = rlb.W[:, None, None]
+    sol = solid()
+    s = s32.astype(np.float64)
+
+    def S(x, force, tau=TAU):
+        F, G = to_pop(x)
+        Fn, Gn = rlb.step(F + w * 1.0, G + w * 0.1, tau, force=force, solid=sol)
+        return to_planes(Fn, Gn)
+
+    force = np.zeros((3, NY, NX))
+    force[0] = FB
+    mu64 = mu.astype(np.float64)
+    # state tangent: z-mirror symmetric (each mirror pair of the full set
+    # perturbed alike), like every state of the one-z-node lattice: the
+    # step of either layout takes its moments and Landau frame over
+    # (t, x, y), so perturbations that break the mirror symmetry are outside
+    # the map it implements (mu needs no such restriction)
+    v17 = rng.standard_normal((34,) + s.shape[1:]) * 1e-2
+    v = np.concatenate([contract(expand(v17[:17], False), full),
+                        contract(expand(v17[17:], False), full)])
+    h = 1e-5
+    Sv = (S(s + h * v, force) - S(s - h * v, force)) / (2 * h)
+    terms = out * _pull(v, full, Q, 1.0)
+    lhs, rhs = terms.sum(), (mu64 * _pull(Sv, full, Q, 1.0)).sum()
+    err = abs(lhs - rhs) / np.abs(terms).sum()
+    print(f"adjoint step: {lhs:.9e} vs {rhs:.9e}  rel {err:.2e}")
+    assert err < 1e-5
+    # force at the node
+    dF = rng.standard_normal((2, NY, NX))
+    hf = 1e-6
+    fp, fm = force.copy(), force.copy()
+    fp[:2] += hf * dF
+    fm[:2] -= hf * dF
+    SF = (S(s, fp) - S(s, fm)) / (2 * hf)
+    tF = acc[..., 0] * dF[0] + acc[..., 1] * dF[1]
+    lhs, rhs = tF.sum(), (mu64 * _pull(SF, full, Q, 1.0)).sum()
+    errF = abs(lhs - rhs) / np.abs(tF).sum()
+    print(f"force adjoint: {lhs:.9e} vs {rhs:.9e}  rel {errF:.2e}")
+    assert errF < 1e-5
+    # relaxation time: d/dtau = -(1/tau^2) d/d(1/tau)
+    ht = 1e-6
+    St = (S(s, force, TAU * (1 + ht)) - S(s, force, TAU * (1 - ht))) / (2 * ht * TAU)
+    tT = -acc[..., 2] / TAU ** 2
+    lhs, rhs = tT.sum(), (mu64 * _pull(St, full, Q, 1.0)).sum()
+    errT = abs(lhs - rhs) / np.abs(tT).sum()
+    print(f"tau adjoint: {lhs:.9e} vs {rhs:.9e}  rel {errT:.2e}")
+    assert errT < 1e-5
