@@ -182,6 +182,10 @@ __device__ __forceinline__ void node_update(const StepShared& sh, Desc& L,
   double Tyy = a.eps_ref * DS::cs2 + (double)myy;
   double Txy = (double)mxy;
   double J0 = a.n_ref + (double)j0, Jx = (double)jx, Jy = (double)jy;
+  // every streamed population enters m00 or j0, so both are finite unless
+  // a population is not (solid nodes included: the test precedes their
+  // rest-frame stand-in)
+  const bool finite = __builtin_isfinite(m00 + j0);
   if constexpr (MASK) {
     if (solid) {
       T00 = a.eps_ref; T0x = 0.0; T0y = 0.0;
@@ -203,7 +207,7 @@ __device__ __forceinline__ void node_update(const StepShared& sh, Desc& L,
   Frame fr{0.0, 1.0, 0.0, 0.0};
   bool ok = landau3<DS::planar>(T00, T0x, T0y, Txx, Txy, Tyy, fr);
   const double n = fr.u0 * J0 - fr.ux * Jx - fr.uy * Jy;
-  ok = ok && (n == n);
+  ok = ok && (n == n) && finite;
 
   // objective density of the streamed state (fluid nodes): the charge
   // current J^x, or pi:pi with pi = T^{kl} - T_eq^{kl} (spatial block)
@@ -226,7 +230,7 @@ __device__ __forceinline__ void node_update(const StepShared& sh, Desc& L,
     const double vals[RLB_FIELD_COUNT] = {
         fr.eps, fr.ux / fr.u0, fr.uy / fr.u0, n, T00, T0x, T0y,
         Txx, Txy, Tyy, J0, Jx, Jy};
-    if (!ok && !solid) atomicOr(a.err, ERR_LANDAU);
+    if (!ok && (!solid || !finite)) atomicOr(a.err, finite ? ERR_LANDAU : ERR_NONFINITE);
     int k = 0;
     const size_t plane = (size_t)nx * ny;
 #pragma unroll
@@ -239,8 +243,9 @@ __device__ __forceinline__ void node_update(const StepShared& sh, Desc& L,
     return;
   } else {
     float fo[Q], go[Q];   // the stored values (open borders only)
-    if (!ok) {   // no rest frame: flag it and leave the node uncollided
-      atomicOr(a.err, ERR_LANDAU);
+    if (!ok) {   // no rest frame, or a non-finite population: flag it and
+                 // leave the node uncollided
+      atomicOr(a.err, finite ? ERR_LANDAU : ERR_NONFINITE);
       static_for<0, Q>([&](auto P) {
         constexpr int p = decltype(P)::value;
         stp<p>(dst, rs, cs, f[p]);

@@ -2,7 +2,8 @@
 lattice (4 x 4, one tile with 60 idle lanes, stirring at |k| = 1), a last
 tile holding a single column (65 x 9, walls, body force), every node solid,
 the fastest stable uniform flow and an unstable one (reported as a
-failure), and a zero-step call."""
+failure), a non-finite population in a fluid or a solid node (reported as
+RLB_ENONFINITE), and a zero-step call."""
 import numpy as np
 import pytest
 
@@ -113,3 +114,35 @@ def test_zero_steps_change_nothing():
     lat.sync()
     assert lat.step_count == 3
     assert torch.equal(lat.save_state().cpu(), before)
+
+
+@pytest.mark.parametrize("value", ["nan", "inf"])
+@pytest.mark.parametrize("where", ["fluid", "solid"], ids=["fluid", "solid"])
+@pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
+def test_nonfinite_population_is_reported(where, value, full):
+    """A state with one non-finite population (loaded from a crafted saved
+    state) is reported as RLB_ENONFINITE by the next step, also when the
+    population sits in a solid node (whose bounce-back would otherwise
+    carry it on unnoticed), and by the field read-out."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import ENONFINITE, RLBError
+    f = workloads.random_fields(80, 40, seed=46, beta=0.01)
+    lat = lattice(f, 0.8, full26=full)
+    lat.add_disks(np.array([[40.0, 20.0, 5.0]]))
+    lat.step(2)
+    lat.sync()
+    buf = lat.save_state()
+    q, row, stride, hb = lat.layout()
+    # the disc centre's downstream neighbours of plane 2 (v_y = +1) are solid too
+    x, y = (40, 20) if where == "solid" else (10, 5)
+    fl = buf[hb:].view(torch.float32)
+    fl[y * stride + (x // 64) * 2 * q * 64 + 2 * 64 + x % 64] = float(value)
+    for read_fields in (False, True):
+        lat.load_state(buf)
+        if read_fields:
+            lat.fields()
+        else:
+            lat.step(1)
+        with pytest.raises(RLBError) as e:
+            lat.sync()
+        assert e.value.status == ENONFINITE, (where, value, read_fields)
