@@ -75,6 +75,19 @@ __device__ __forceinline__ void stp(float* base, int64_t r, uint32_t c, float v)
   __builtin_nontemporal_store(v, (gfloat*)(b + c));
 }
 
+// Four-tap interpolation t0 a + t1 b + t2 c + t3 d with t0 + t1 + t2 + t3 = 1,
+// as a + t1 (b - a) + t2 (c - a) + t3 (d - a) (exact for a = b = c = d).
+// SYM: t1 = t2 (|vx| = |vy|), so t1 ((b + c) - 2a) + t3 (d - a).
+template <bool SYM>
+__device__ __forceinline__ float bilinear(float a, float b, float c, float d, const float* tap) {
+  if constexpr (SYM) {
+    return __builtin_fmaf(tap[3], d - a, __builtin_fmaf(tap[1], __builtin_fmaf(-2.0f, a, b + c), a));
+  } else {
+    return __builtin_fmaf(tap[3], d - a,
+                          __builtin_fmaf(tap[2], c - a, __builtin_fmaf(tap[1], b - a, a)));
+  }
+}
+
 template <class DS, int P>
 struct Taps {
   static constexpr double vx = DS::vx[P], vy = DS::vy[P];
@@ -89,6 +102,13 @@ struct Taps {
 // tap[0..3] on (x, y), (x - sx, y), (x, y - sy), (x - sx, y - sy).  REV
 // takes the same weights at x + delta instead (the transposed pull, used
 // by the adjoint).  With UNIT (cfl = 1) a unit component is a plain shift.
+// The weights sum to exactly 1, so the sum is formed as the first tap's
+// value plus weighted differences, a + t1 (b - a) + t2 (c - a) + t3 (d - a)
+// (with |vx| = |vy| the two middle weights are equal and share one
+// product): a uniform field streams unchanged bit for bit.  (Summed as
+// t0 a + t1 b + t2 c + t3 d, the float32 products moved a uniform value by
+// an ulp at some values, the same at every node, and the conserved totals
+// drifted at a steady rate.)
 template <class DS, bool UNIT, int P, int PL, bool REV>
 __device__ __forceinline__ float pull(const float* __restrict__ base, const Nbr& n,
                                       const float* tap) {
@@ -104,12 +124,15 @@ __device__ __forceinline__ float pull(const float* __restrict__ base, const Nbr&
   } else if constexpr (UNIT && T::unit_y) {
     return ldp<PL>(base, ry, c0);
   } else if constexpr (T::sy == 0) {
-    return tap[0] * ldp<PL>(base, r0, c0) + tap[1] * ldp<PL>(base, r0, cx);
+    const float a = ldp<PL>(base, r0, c0);
+    return a + tap[1] * (ldp<PL>(base, r0, cx) - a);
   } else if constexpr (T::sx == 0) {
-    return tap[0] * ldp<PL>(base, r0, c0) + tap[2] * ldp<PL>(base, ry, c0);
+    const float a = ldp<PL>(base, r0, c0);
+    return a + tap[2] * (ldp<PL>(base, ry, c0) - a);
   } else {
-    return tap[0] * ldp<PL>(base, r0, c0) + tap[1] * ldp<PL>(base, r0, cx) +
-           tap[2] * ldp<PL>(base, ry, c0) + tap[3] * ldp<PL>(base, ry, cx);
+    return bilinear<DS::vx[P] == DS::vy[P] || DS::vx[P] == -DS::vy[P]>(
+        ldp<PL>(base, r0, c0), ldp<PL>(base, r0, cx), ldp<PL>(base, ry, c0), ldp<PL>(base, ry, cx),
+        tap);
   }
 }
 
@@ -153,13 +176,14 @@ __device__ __forceinline__ float pull_wide(const float* __restrict__ base, const
     const uint32_t cf = sx == 0 ? n.c[2] : (mx ? n.c[2 - 2 * sx] : n.c[2 - sx]);
     const int64_t rn = sy == 0 ? n.r[2] : (my ? n.r[2 - sy] : n.r[2]);
     const int64_t rf = sy == 0 ? n.r[2] : (my ? n.r[2 - 2 * sy] : n.r[2 - sy]);
+    const float a = ldp<PL>(base, rn, cn);   // differences from the near tap, as pull
     if constexpr (sy == 0) {
-      return tap[0] * ldp<PL>(base, rn, cn) + tap[1] * ldp<PL>(base, rn, cf);
+      return a + tap[1] * (ldp<PL>(base, rn, cf) - a);
     } else if constexpr (sx == 0) {
-      return tap[0] * ldp<PL>(base, rn, cn) + tap[2] * ldp<PL>(base, rf, cn);
+      return a + tap[2] * (ldp<PL>(base, rf, cn) - a);
     } else {
-      return tap[0] * ldp<PL>(base, rn, cn) + tap[1] * ldp<PL>(base, rn, cf) +
-             tap[2] * ldp<PL>(base, rf, cn) + tap[3] * ldp<PL>(base, rf, cf);
+      return bilinear<DS::vx[P] == DS::vy[P] || DS::vx[P] == -DS::vy[P]>(
+          a, ldp<PL>(base, rn, cf), ldp<PL>(base, rf, cn), ldp<PL>(base, rf, cf), tap);
     }
   }
 }
