@@ -504,9 +504,8 @@ static hipError_t launch_one_step(rlb_lattice* lat, const StirArgs& sa, int forc
                                   int slot, double* rec = nullptr, int rec_x = 0) {
   hipError_t e = hipSuccess;
   if (lat->stir) {
-    if ((e = launch_stir_draw(sa, -1, lat->stream)) != hipSuccess) return e;
-    if ((e = launch_stir_table(sa, lat->stream)) != hipSuccess) return e;
-    if ((e = launch_stir_synth(sa, lat->stream)) != hipSuccess) return e;
+    if ((e = launch_stir_table(sa, -1, lat->stream)) != hipSuccess) return e;
+    if ((e = launch_stir_synth(sa, true, lat->stream)) != hipSuccess) return e;
   }
   if (slot >= 0 && (e = hipEventRecord(lat->ev[slot][0], lat->stream)) != hipSuccess) return e;
   const int mode = step_mode(lat);
@@ -878,9 +877,8 @@ rlb_status rlb_stirring_field(rlb_lattice* lat, int64_t step, float* d_out) {
   if (step < 0) return fail(RLB_EINVAL, "step must be >= 0");
   if (!d_out || !aligned(d_out, 4)) return fail(RLB_EINVAL, "output must be a 4-byte aligned device pointer");
   const StirArgs a = stir_args(lat);
-  HIP_TRY(launch_stir_draw(a, step, lat->stream), "stirring draw");
-  HIP_TRY(launch_stir_table(a, lat->stream), "stirring table");
-  HIP_TRY(launch_stir_synth(a, lat->stream), "stirring synthesis");
+  HIP_TRY(launch_stir_table(a, step, lat->stream), "stirring table");
+  HIP_TRY(launch_stir_synth(a, false, lat->stream), "stirring synthesis");
   const size_t plane = (size_t)lat->p.nx * lat->p.ny;
   for (int c = 0; c < 2; ++c)
     HIP_TRY(hipMemcpy2DAsync(d_out + c * plane, sizeof(float) * lat->p.nx, lat->force + c * lat->pitch,

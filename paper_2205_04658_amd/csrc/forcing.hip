@@ -2,13 +2,14 @@
 // on the spectral lattice inside the driving band, transformed to
 // configuration space every step).
 //
-// Per step: (1) one workgroup draws the complex coefficients of every
-// half-shell mode from Philox4x64-10 + Box-Muller in float64 (counter
-// (m, step, 0, 0), key (seed, stream)); (2) one wavefront per row folds the
-// shell sum along ky into the row's real trigonometric series in x,
-// a_k cos(k th) + b_k sin(k th), th = 2 pi x / nx, summing modes in a fixed
-// order; (3) the synthesis kernel evaluates the series at every node and
-// writes the two force planes the step kernel reads.  The synthesis is a
+// Per step: (1) the series kernel draws the complex coefficients of the
+// half-shell modes from Philox4x64-10 + Box-Muller in float64 (counter
+// (m, step, 0, 0), key (seed, stream)) -- each workgroup those of the modes
+// it needs -- and folds the shell sum along ky into each row's real
+// trigonometric series in x, a_k cos(k th) + b_k sin(k th), th = 2 pi x / nx,
+// summing modes in a fixed order; (2) the synthesis kernel evaluates the
+// series at every node, writes the two force planes the step kernel reads
+// and advances the device step counter.  The synthesis is a
 // dense product, F_c(y, x) = sum_j A_c(y, j) T(j, x) over the 2 (K + 1)
 // slots j = (k, cos | sin), so it runs on the matrix cores.  Both operands
 // are split into float16 hi + lo parts (the coefficients scaled by a power
@@ -24,25 +25,30 @@
 
 namespace rlb {
 
-__global__ __launch_bounds__(256) void stir_draw_kernel(const StirArgs a,
-                                                        int64_t fixed_step) {
-  __shared__ int64_t s_step;
-  if (threadIdx.x == 0) s_step = fixed_step >= 0 ? fixed_step : *a.dstep;
-  __syncthreads();
-  const int64_t t = s_step;
+// Coefficients (Re Fx, Im Fx, Re Fy, Im Fy) of half-shell mode m at step t.
+__device__ __forceinline__ void draw_mode(const StirArgs& a, int m, int64_t t, double c[4]) {
+  const U64x4 r = philox4x64_10((uint64_t)m, (uint64_t)t, 0, 0, a.seed, a.stream);
+  double z0, z1, z2, z3;
+  box_muller(r.v[0], r.v[1], z0, z1);
+  box_muller(r.v[2], r.v[3], z2, z3);
+  c[0] = a.amplitude * z0;
+  c[1] = a.amplitude * z1;
+  c[2] = a.amplitude * z2;
+  c[3] = a.amplitude * z3;
+}
+
+// Every mode's coefficients at step `step` into a.coef (the coefficient
+// read-out; the step's own series kernel draws what it needs itself).
+__global__ __launch_bounds__(256) void stir_draw_kernel(const StirArgs a, int64_t step) {
   for (int m = threadIdx.x; m < a.nmodes; m += blockDim.x) {
-    const U64x4 r = philox4x64_10((uint64_t)m, (uint64_t)t, 0, 0, a.seed, a.stream);
-    double z0, z1, z2, z3;
-    box_muller(r.v[0], r.v[1], z0, z1);
-    box_muller(r.v[2], r.v[3], z2, z3);
-    double* c = a.coef + 4 * (size_t)m;
-    c[0] = a.amplitude * z0;
-    c[1] = a.amplitude * z1;
-    c[2] = a.amplitude * z2;
-    c[3] = a.amplitude * z3;
+    double c[4];
+    draw_mode(a, m, step, c);
+    double* o = a.coef + 4 * (size_t)m;
+    o[0] = c[0];
+    o[1] = c[1];
+    o[2] = c[2];
+    o[3] = c[3];
   }
-  __syncthreads();
-  if (fixed_step < 0 && threadIdx.x == 0) *a.dstep = t + 1;
 }
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
@@ -57,44 +63,64 @@ __device__ __forceinline__ void split16(double v, _Float16& hi, _Float16& lo) {
 
 // Series coefficients: (a_k, b_k) of F^x and F^y for every |kx| = k and row
 // y, times the lattice's power-of-two scale, in the synthesis's operand
-// order (see StirArgs::table).  One thread per (k, y) sums the modes of its
-// bin in their fixed order: mode (kx, ky) with coefficient c contributes
-// prod = 2 c e^{2 pi i ky y / ny} to cos(k th) with Re(prod) and to
-// sin(k th) with -sign(kx) Im(prod).  Rows k past K are written as zeros.
-__global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a) {
+// order (see StirArgs::table).  A workgroup (one wavefront, 64 rows of one
+// k) first draws the coefficients of its bin's modes at the step (the
+// device counter, or fixed_step >= 0), 64 modes at a time into LDS; then
+// each thread sums the modes of the bin in their fixed order: mode
+// (kx, ky) with coefficient c contributes prod = 2 c e^{2 pi i ky y / ny}
+// to cos(k th) with Re(prod) and to sin(k th) with -sign(kx) Im(prod).
+// Rows k past K are written as zeros.  (Drawing in this kernel instead of
+// a one-workgroup draw kernel before it: 14.8 -> 12 us per step at 4096^2.)
+__global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a, int64_t fixed_step) {
+  __shared__ double s_c[64][4];
   const int y = blockIdx.x * 64 + threadIdx.x;
   const int k = blockIdx.y;   // 0 .. 8 chunks(K) - 1
-  if (y >= a.ny) return;
+  const bool row = y < a.ny;
   double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
-  // the bin's modes and their drawn coefficients are the same for every
-  // thread of the workgroup and read-only here (written by earlier
-  // launches): read them through the constant address space, i.e. with
-  // scalar loads
+  // the bin's modes and the step are the same for every thread of the
+  // workgroup and read-only here (written by earlier launches): read them
+  // through the constant address space, i.e. with scalar loads
   typedef const __attribute__((address_space(4))) int CInt;
-  typedef const __attribute__((address_space(4))) double CDouble;
+  typedef const __attribute__((address_space(4))) int64_t CI64;
   CInt* bins = (CInt*)a.bins;
   CInt* modes = (CInt*)a.modes;
-  CDouble* coef = (CDouble*)a.coef;
+  const int64_t t = fixed_step >= 0 ? fixed_step : *(CI64*)a.dstep;
+  const int j0 = k <= a.K ? bins[k] : 0;
   const int j1 = k <= a.K ? bins[k + 1] : 0;
-  // unrolled so that several phase-table reads are in flight at once
+  for (int jc = j0; jc < j1; jc += 64) {
+    const int n = min(64, j1 - jc);
+    if ((int)threadIdx.x < n) {
+      double c[4];
+      draw_mode(a, modes[4 * (jc + threadIdx.x)], t, c);
+      s_c[threadIdx.x][0] = c[0];
+      s_c[threadIdx.x][1] = c[1];
+      s_c[threadIdx.x][2] = c[2];
+      s_c[threadIdx.x][3] = c[3];
+    }
+    __syncthreads();
+    // unrolled so that several phase-table reads are in flight at once
 #pragma unroll 4
-  for (int j = k <= a.K ? bins[k] : 0; j < j1; ++j) {
-    const int md_x = modes[4 * j], md_y = modes[4 * j + 1], md_z = modes[4 * j + 2];
-    // e^{2 pi i ky y / ny} from the phase table, index reduced exactly
-    // (0 <= ky <= 63 and y < ny < 2^24: the product fits 32 bits)
-    const double2 e = a.phase[(unsigned)(md_z * y) % (unsigned)a.ny];
-    const double cs = e.x, sn = e.y;
-    CDouble* c = coef + 4 * (size_t)md_x;
-    const double pxr = 2.0 * (c[0] * cs - c[1] * sn);
-    const double pxi = 2.0 * (c[0] * sn + c[1] * cs);
-    const double pyr = 2.0 * (c[2] * cs - c[3] * sn);
-    const double pyi = 2.0 * (c[2] * sn + c[3] * cs);
-    const double sg = md_y > 0 ? -1.0 : 1.0;   // kx = 0 has no sine part
-    ax += pxr;
-    bx += sg * pxi;
-    ay += pyr;
-    by += sg * pyi;
+    for (int jj = 0; jj < n; ++jj) {
+      const int j = jc + jj;
+      const int md_y = modes[4 * j + 1], md_z = modes[4 * j + 2];
+      // e^{2 pi i ky y / ny} from the phase table, index reduced exactly
+      // (0 <= ky <= 63 and y < ny < 2^24: the product fits 32 bits)
+      const double2 e = a.phase[row ? (unsigned)(md_z * y) % (unsigned)a.ny : 0u];
+      const double cs = e.x, sn = e.y;
+      const double* c = s_c[jj];
+      const double pxr = 2.0 * (c[0] * cs - c[1] * sn);
+      const double pxi = 2.0 * (c[0] * sn + c[1] * cs);
+      const double pyr = 2.0 * (c[2] * cs - c[3] * sn);
+      const double pyi = 2.0 * (c[2] * sn + c[3] * cs);
+      const double sg = md_y > 0 ? -1.0 : 1.0;   // kx = 0 has no sine part
+      ax += pxr;
+      bx += sg * pxi;
+      ay += pyr;
+      by += sg * pyi;
+    }
+    __syncthreads();
   }
+  if (!row) return;
   if (k == 0) bx = by = 0.0;
   const double sc = (double)a.scale;
   const double v[2][2] = {{ax * sc, bx * sc}, {ay * sc, by * sc}};
@@ -145,14 +171,22 @@ static inline int synth_chunks(int K) { return (K + 8) >> 3; }
 // for chunk c: exactly one 16-byte table item each.  Accumulator element i
 // of lane l is block row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
 // Rows and columns past the lattice are clamped on load and skipped on
-// store.
+// store.  The kernel advances the device step counter when `advance` is set
+// (the series kernel of the next step reads it).
+// Measured at 4096^2 against this form (36 us): 16-byte stores through a
+// per-wavefront LDS tile, the same; the transposed product with 16-byte
+// stores straight from the accumulators (32-byte pieces per row), 148 us;
+// 32 x 32 tiles (6 waves per SIMD), 49 us; 32 x 128 tiles (1 wave per
+// SIMD), 41 us.
 __global__ __launch_bounds__(64 * kSynthWaves) void stir_synth_kernel(
     const uint4* __restrict__ table, const uint4* __restrict__ tw, float* __restrict__ force,
-    int64_t force_pitch, int nchunks, int nx, int ny, int row_pitch, float inv_scale) {
+    int64_t force_pitch, int nchunks, int nx, int ny, int row_pitch, float inv_scale,
+    int64_t* dstep, int advance) {
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5, l32 = lane & 31;
   const int tiles_x = (nx + kSynthWaveCols - 1) / kSynthWaveCols;
   const int tile = blockIdx.x * kSynthWaves + (threadIdx.x >> 6);
+  if (advance && tile == 0 && lane == 0) *dstep += 1;
   const int ty = tile / tiles_x;
   const int y0 = ty * 32;
   const int xw = (tile - ty * tiles_x) * kSynthWaveCols;
@@ -233,22 +267,22 @@ __global__ void set_i64_kernel(int64_t* p, int64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-hipError_t launch_stir_draw(const StirArgs& a, int64_t fixed_step,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(stir_draw_kernel, dim3(1), dim3(256), 0, s, a, fixed_step);
+hipError_t launch_stir_draw(const StirArgs& a, int64_t step, hipStream_t s) {
+  hipLaunchKernelGGL(stir_draw_kernel, dim3(1), dim3(256), 0, s, a, step);
   return hipGetLastError();
 }
 
-hipError_t launch_stir_table(const StirArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(stir_table_kernel, dim3((a.ny + 63) / 64, 8 * synth_chunks(a.K)), dim3(64), 0, s, a);
+hipError_t launch_stir_table(const StirArgs& a, int64_t fixed_step, hipStream_t s) {
+  hipLaunchKernelGGL(stir_table_kernel, dim3((a.ny + 63) / 64, 8 * synth_chunks(a.K)), dim3(64), 0,
+                     s, a, fixed_step);
   return hipGetLastError();
 }
 
-hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s) {
+hipError_t launch_stir_synth(const StirArgs& a, bool advance, hipStream_t s) {
   const int tiles = ((a.nx + kSynthWaveCols - 1) / kSynthWaveCols) * ((a.ny + 31) / 32);
   hipLaunchKernelGGL(stir_synth_kernel, dim3((tiles + kSynthWaves - 1) / kSynthWaves),
                      dim3(64 * kSynthWaves), 0, s, a.table, a.twiddle, a.force, a.force_pitch,
-                     synth_chunks(a.K), a.nx, a.ny, a.row, a.inv_scale);
+                     synth_chunks(a.K), a.nx, a.ny, a.row, a.inv_scale, a.dstep, advance ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -283,10 +283,12 @@ hipError_t launch_walls(const rlb_lattice* lat);
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
 
 // forcing.hip
-hipError_t launch_stir_draw(const StirArgs& a, int64_t fixed_step,
-                            hipStream_t s);
-hipError_t launch_stir_table(const StirArgs& a, hipStream_t s);
-hipError_t launch_stir_synth(const StirArgs& a, hipStream_t s);
+// Every mode's coefficients at `step` into a.coef.
+hipError_t launch_stir_draw(const StirArgs& a, int64_t step, hipStream_t s);
+// Draw and row series of the step on the device counter (fixed_step < 0)
+// or of fixed_step; the synthesis, advancing the counter when `advance`.
+hipError_t launch_stir_table(const StirArgs& a, int64_t fixed_step, hipStream_t s);
+hipError_t launch_stir_synth(const StirArgs& a, bool advance, hipStream_t s);
 hipError_t launch_phase(const rlb_lattice* lat);
 hipError_t launch_twiddle(uint4* tw, int K, int nx, hipStream_t s);
 hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count,
@@ -296,12 +298,12 @@ hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
 // adjoint.hip
 hipError_t launch_adjoint(int Q, bool unit, bool mask, const AdjArgs& a, hipStream_t s);
 hipError_t launch_objective(int Q, bool unit, bool mask, const ObjArgs& a, int grid, hipStream_t s);
-hipError_t launch_basis_force(const double* modes, const double* amps, int M, int nx, int ny,
-                              int row, int64_t pitch, float* force, hipStream_t s);
-hipError_t launch_grad_reduce(const double2* acc_f, const double* acc_itau, const double* modes,
 // out = P^T mu (the adjoint kernel's transposed pull alone)
 hipError_t launch_transpose_pull(int Q, bool unit, const float* mu, float* out, int nx, int ny,
                                  int row, const StepShared& sh, hipStream_t s);
+hipError_t launch_basis_force(const double* modes, const double* amps, int M, int nx, int ny,
+                              int row, int64_t pitch, float* force, hipStream_t s);
+hipError_t launch_grad_reduce(const double2* acc_f, const double* acc_itau, const double* modes,
                               int M, int nx, int ny, double tau, double* partial, int cols,
                               double* out, hipStream_t s);
 hipError_t launch_sum_rows(const double* partial, int cols, int rows, double scale, double* out,

@@ -29,15 +29,21 @@ def test_philox_bit_exact():
             assert tuple(int(v) for v in got[m]) == want, (k0, k1, c1, m)
 
 
-@pytest.mark.parametrize("shell", [(7, 9, 1e-5, 2205), (31, 33, 5e-6, 4658), (0.5, 3.2, 1e-3, 1)])
-def test_stirring_coefficients_and_field(shell):
+@pytest.mark.parametrize("shell,size", [((7, 9, 1e-5, 2205), (96, 80)), ((31, 33, 5e-6, 4658), (128, 128)),
+                                        ((0.5, 3.2, 1e-3, 1), (96, 80)), ((2, 5, 1e-4, 3), (200, 72))])
+def test_stirring_coefficients_and_field(shell, size):
+    """Coefficients bit for bit with the oracle's draw (to the last bits of
+    Box-Muller), and the synthesised field against the oracle's direct
+    shell sum.  Field bound: the float16 hi + lo operands carry 22
+    significant bits (each within 2^-22 = 2.4e-7 of its value), the product
+    drops lo * lo (2^-22 relative), and the float32 sums over 68 slots add
+    a few 2^-24; measured max error 7.1e-7 of the field's rms over these
+    shells and steps, bound 2e-6 (about 3x).  200 columns: the synthesis
+    tiles reach past the row pitch."""
     torch = need_gpu()
-    nx, ny = 96, 80
+    nx, ny = size
     lat = make_lattice(workloads.uniform(nx, ny), 0.8)
     kmin, kmax, amp, seed = shell
-    if kmax >= min(nx, ny) / 2:
-        nx = ny = 128
-        lat = make_lattice(workloads.uniform(nx, ny), 0.8)
     lat.set_stirring(kmin, kmax, amp, seed)
     modes = forcing.shell_modes(kmin, kmax)
     for step in (0, 7, 123456):
@@ -49,7 +55,9 @@ def test_stirring_coefficients_and_field(shell):
         fld = lat.stirring_field(step).double().cpu().numpy()
         ref = forcing.synthesize(modes, cx, cy, nx, ny)
         rms = np.sqrt((ref ** 2).mean())
-        assert np.abs(fld - ref).max() < 2e-5 * rms
+        print(f"stirring field {shell} {size} step {step}: max error / rms "
+              f"{np.abs(fld - ref).max() / rms:.3e}")
+        assert np.abs(fld - ref).max() < 2e-6 * rms
 
 
 def test_init_fields_match():
