@@ -336,9 +336,12 @@ rlb_status rlb_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count,
                       uint64_t* d_out, void* hip_stream);
 
 /* Per-launch timing of the main step kernel with HIP events on the lattice
- * stream.  rlb_timing(lat, 1) starts recording (and clears totals);
- * rlb_timing_read synchronises and returns the summed kernel time in ms and
- * the number of timed launches. */
+ * stream.  rlb_timing(lat, k), k >= 1, starts recording the step kernel of
+ * every k-th step launched kernel by kernel (k = 1: every step; events
+ * around a launch keep the next kernel from starting early, so sampling
+ * disturbs the timed run less) and clears the totals; rlb_timing(lat, 0)
+ * stops.  rlb_timing_read synchronises and returns the summed kernel time
+ * in ms and the number of timed launches.  RLB_EINVAL for k < 0. */
 rlb_status rlb_timing(rlb_lattice* lat, int32_t enable);
 rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches);
 
@@ -518,9 +521,6 @@ rlb_status rlb_adjoint_workspace_bytes(const rlb_lattice* lat, const rlb_adjoint
 rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d_ws,
                            size_t bytes, double* h_objective, double* h_grad);
 
-/* A plain device copy of `bytes` (multiple of 16) for bandwidth calibration. */
-rlb_status rlb_copy_probe(const void* d_src, void* d_dst, size_t bytes,
-                          void* hip_stream);
 /* The two linear maps one reverse step of rlb_adjoint_run applies, on caller
  * buffers, for checking them by the dot-product identity
  * <A^T mu, v> = <mu, A v> against a tangent of the forward step:
@@ -549,6 +549,9 @@ enum { RLB_ADJ_STEP = 0, RLB_ADJ_PULL_T = 1 };
 rlb_status rlb_adjoint_apply(rlb_lattice* lat, int32_t op, const float* d_state,
                              const float* d_mu, float* d_out, double* d_acc);
 
+/* A plain device copy of `bytes` (multiple of 16) for bandwidth calibration. */
+rlb_status rlb_copy_probe(const void* d_src, void* d_dst, size_t bytes,
+                          void* hip_stream);
 
 /* Human-readable message of the last failure on this thread. */
 const char* rlb_last_error(void);

@@ -520,8 +520,8 @@ static hipError_t launch_one_step(rlb_lattice* lat, const StirArgs& sa, int forc
 static rlb_status step_direct(rlb_lattice* lat, const StirArgs& sa, int force,
                               double* rec = nullptr, int rec_x = 0) {
   int slot = -1;
-  if (lat->timing) {
-    slot = (int)(lat->step % kEvRing);
+  if (lat->timing && lat->step % lat->timing_every == 0) {
+    slot = (int)((lat->step / lat->timing_every) % kEvRing);
     if (rlb_status s = drain_event(lat, slot)) return s;
   }
   HIP_TRY(launch_one_step(lat, sa, force, lat->cur, slot, rec, rec_x), "step");
@@ -898,7 +898,9 @@ rlb_status rlb_philox(uint64_t k0, uint64_t k1, uint64_t c1, int64_t count, uint
 rlb_status rlb_timing(rlb_lattice* lat, int32_t enable) {
   if (rlb_status s = check_lat(lat)) return s;
   if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: use the batch's timing (rlb_batch_timing)");
+  if (enable < 0) return fail(RLB_EINVAL, "enable must be >= 0");
   if (enable) {
+    lat->timing_every = enable;
     if (!lat->ev[0][0]) {
       for (int i = 0; i < kEvRing; ++i)
         for (int j = 0; j < 2; ++j) HIP_TRY(hipEventCreate(&lat->ev[i][j]), "event create");

@@ -206,8 +206,9 @@ struct rlb_lattice {
   float tap[rlb::kMaxQ][4];
   uint8_t shift[rlb::kMaxQ][2];   // whole-cell tap shifts (cfl > 1)
   int64_t step;
-  // timing of the main step kernel
+  // timing of the main step kernel (of every timing_every-th step)
   bool timing;
+  int32_t timing_every;
   int64_t timed_launches;
   double timed_ms;
   hipEvent_t ev[16][2];   // ring of (start, end) pairs

@@ -437,8 +437,9 @@ class Lattice:
         check(lib().rlb_autotune(self._h, int(trials), out, 64))
         return _tune_rows(out)
 
-    def timing(self, enable=True):
-        check(lib().rlb_timing(self._h, 1 if enable else 0))
+    def timing(self, enable=True, every=1):
+        """Time the step kernel of every `every`-th step (rlb_timing)."""
+        check(lib().rlb_timing(self._h, int(every) if enable else 0))
 
     def timing_read(self):
         ms, n = _d(), _i64()
