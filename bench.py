@@ -4,8 +4,9 @@
 
 Workload: forced turbulence, 4096 x 4096 periodic lattice, tau = 0.52,
 k-shell stirring 31 <= |k| <= 33 (412 modes), amplitude 5e-6, seed 4658,
-initially at rest (eps = 1, n = 0.1).  One step = stirring draw + series
-table + the fused step kernel over every node.  Prints one JSON line with
+initially at rest (eps = 1, n = 0.1).  One step = the stirring draw and
+series kernel + the stirring synthesis + the fused step kernel over every
+node.  Prints one JSON line with
 MLUPS (whole job), the roofline of the step kernel (HIP-event timed per
 launch inside the library), the plain copy bandwidth on the same GPU and
 the FP64 oracle's host throughput on a bounded sample of the same workload.
@@ -70,18 +71,10 @@ def copy_probe_gbs(torch, rlb, nbytes=2 << 30, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(seconds=15.0):
-    """Time the FP64 oracle (one thread) on a 256 x 256 lattice of the same
-    forced workload (same tau, shell, amplitude and seed) in a child
-    process pinned to one core."""
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    code = f"""
+_ORACLE_SAMPLE = """
 import os, sys, time, json
-sys.path.insert(0, {ROOT!r})
-try:
-    os.sched_setaffinity(0, {{sorted(os.sched_getaffinity(0))[0]}})
-except Exception:
-    pass
+sys.path.insert(0, {root!r})
+os.sched_setaffinity(0, {{{core}}})
 import numpy as np
 from oracle import rlb, forcing
 from paper_2205_04658_amd import workloads
@@ -100,14 +93,73 @@ while True:
         break
 print(json.dumps(dict(steps=steps, seconds=el, cells=n * n)))
 """
-    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
-    if r.returncode != 0:
-        return {"error": r.stderr[-500:]}
-    d = json.loads(r.stdout.strip().splitlines()[-1])
-    mlups = d["cells"] * d["steps"] / d["seconds"] / 1e6
-    return {"value": mlups, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+
+_ORACLE_SHEAR = """
+import os, sys, time, json
+sys.path.insert(0, {root!r})
+os.sched_setaffinity(0, {{{core}}})
+import numpy as np
+from oracle import rlb
+from paper_2205_04658_amd import workloads
+c = workloads.SHEAR
+f = workloads.shear_wave(c["nx"], c["ny"], c["amp"])
+F, G = rlb.initial_state(*(f[k].astype(np.float64) for k in ("eps", "bx", "by", "n")))
+t0 = time.perf_counter()
+for _ in range(c["steps"]):
+    F, G = rlb.step(F, G, c["tau"])
+el = time.perf_counter() - t0
+print(json.dumps(dict(steps=c["steps"], seconds=el, cells=c["nx"] * c["ny"])))
+"""
+
+
+def host_cpu():
+    """The host's CPU model and logical CPU count (and how many this process
+    may use)."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline_start(seconds=15.0):
+    """Start the FP64 oracle timings on the host, each in a child process
+    pinned to a core of its own with one thread, so that they run while the
+    GPU measurements do: (1) 256 x 256 of the forced workload (same tau,
+    shell, amplitude and seed) for about `seconds`; (2) the whole 64 x 64
+    shear-wave workload, 1000 steps."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cores = sorted(os.sched_getaffinity(0))
+    procs = {}
+    for name, code, core in (("sample", _ORACLE_SAMPLE, cores[0]), ("shear", _ORACLE_SHEAR, cores[-1])):
+        src = code.format(root=ROOT, core=core, seconds=seconds)
+        procs[name] = subprocess.Popen([sys.executable, "-c", src], env=env, stdout=subprocess.PIPE,
+                                       stderr=subprocess.PIPE, text=True)
+    return procs
+
+
+def cpu_baseline_finish(procs):
+    res = {}
+    for name, p in procs.items():
+        out, err = p.communicate(timeout=900)
+        if p.returncode != 0:
+            return {"error": f"{name}: {err[-500:]}"}
+        d = json.loads(out.strip().splitlines()[-1])
+        d["mlups"] = d["cells"] * d["steps"] / d["seconds"] / 1e6
+        res[name] = d
+    s, w = res["sample"], res["shear"]
+    return {"value": s["mlups"], "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"256x256 forced lattice (tau 0.52, shell 31-33, amp 5e-6, seed 4658), "
-                      f"{d['steps']} steps in {d['seconds']:.1f} s, float64 NumPy, 1 thread"}
+                      f"{s['steps']} steps in {s['seconds']:.1f} s, float64 NumPy, 1 thread",
+            "shear_wave_64x64_1000_steps": {"seconds": w["seconds"], "mlups": w["mlups"],
+                                           "threads": 1},
+            "host": host_cpu(),
+            "note": "each timing single-threaded on a core of its own, run while the GPU "
+                    "measurements ran"}
 
 
 def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=None, cfl=1.0,
@@ -424,6 +476,7 @@ def main():
     from paper_2205_04658_amd import rlb, workloads
     rlb.lib()
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    cpu_procs = None if a.no_cpu_baseline else cpu_baseline_start()
     shape = tuple(int(v) for v in a.shape.split(",")) if a.shape else None
     main_run = run_plain(torch, rlb, workloads, a.layout, a.steps, a.warmup, shape,
                          repeats=a.repeats)
@@ -464,7 +517,11 @@ def main():
         adjoint = run_adjoint(torch, rlb, workloads)
         adjoint["vs_plain"] = adjoint["adjoint"]["mlups"] / main_run["mlups"]
     copy_gbs = copy_probe_gbs(torch, rlb)
-    cpu = None if a.no_cpu_baseline else cpu_baseline()
+    cpu = None if cpu_procs is None else cpu_baseline_finish(cpu_procs)
+    # the whole step: the step kernel's bytes plus the stirring planes the
+    # synthesis writes (the series kernel's few MB are left out)
+    whole_bytes = main_run["bytes_per_cell"] + 8
+    whole_gbs = whole_bytes * 4096 * 4096 / (main_run["ms_per_step"] * 1e-3) / 1e9
     r = main_run
     line = {
         "metric": METRIC, "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": a.steps,
@@ -482,6 +539,8 @@ def main():
                      "unit": "GB/s", "frac": r["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": r["traffic"], "kernel_ms": r["kernel_ms"],
                      "bytes_per_cell": r["bytes_per_cell"], "bytes_per_launch": r["bytes_per_launch"]},
+        "whole_step": {"bytes_per_cell": whole_bytes, "achieved": whole_gbs, "unit": "GB/s",
+                       "frac": whole_gbs / HBM_PEAK_GBS, "ms_per_step": r["ms_per_step"]},
         "repeats": r.get("repeats"),
         "copy_probe_gbs": copy_gbs,
         "batched": batched,

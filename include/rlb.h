@@ -222,7 +222,7 @@ rlb_status rlb_load_state(rlb_lattice* lat, const void* d_buf, size_t bytes);
 rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitch,
                       int64_t* row_stride, size_t* header_bytes);
 
-/* Open x borders of a lattice created with RLB_OPEN_X (Ch. 6, "Model and
+/* Open x borders of a lattice created with RLB_OPEN_X (Ch. 5, "Model and
  * Methods": a fixed velocity enters along the inflow border, the lateral
  * borders are periodic).  After every step:
  *   - velocity inlet, column x = 0: equilibrium at 3-velocity (bx, by) and
@@ -242,7 +242,7 @@ rlb_status rlb_layout(const rlb_lattice* lat, int32_t* planes, int32_t* row_pitc
 rlb_status rlb_set_open_borders(rlb_lattice* lat, double bx, double by, double n_in,
                                 double eps_out);
 
-/* Current density at column x (Ch. 6: j recorded at the outflow border and
+/* Current density at column x (Ch. 5: j recorded at the outflow border and
  * along the channel): d_out[0] = (1/ny) sum_y J^x(x, y) of the current step
  * (streamed populations, as rlb_read_fields; solid nodes count as zero),
  * float64, written asynchronously on the lattice stream.  Collect a time
@@ -423,7 +423,7 @@ rlb_status rlb_batch_step(rlb_batch* batch, int64_t nsteps);
 rlb_status rlb_batch_record_workspace_bytes(const rlb_batch* batch, int32_t chunk, size_t* bytes);
 
 /* nsteps batched steps that also record every member's current density
- * (Ch. 6: j(t) of each impurity placement): d_series[b * stride + t] = j
+ * (Ch. 5: j(t) of each impurity placement): d_series[b * stride + t] = j
  * of member b's state before step t+1 at column x, t = 0 .. nsteps-1,
  * bitwise the series rlb_record_current gives for an open-channel member
  * stepped alone, and otherwise rlb_column_current before each step.  x >= 0 names the same column in every member; x < 0 counts

@@ -39,7 +39,7 @@ def enstrophy(bx, by):
 
 
 # --------------------------------------------------------------------------
-# Current-density fluctuations (Ch. 6, "Model and Methods": j(t) at the
+# Current-density fluctuations (Ch. 5, "Model and Methods": j(t) at the
 # outflow border, j(x) along the sampling region, and their spectra)
 # --------------------------------------------------------------------------
 def column_current(fields, x):

@@ -270,7 +270,7 @@ def step(F, G, tau, cfl=1.0, force=None, solid=None, collision="aw", open_x=None
       Ch. 3 eq. lbe_coll_term); used only as a negative control.
     * tau: a constant, or a ViscosityRelaxation giving tau(x) from the
       node's Landau energy density.
-    * open_x = (beta_x, beta_y, n_in, eps_out): open x borders (Ch. 6
+    * open_x = (beta_x, beta_y, n_in, eps_out): open x borders (Ch. 5
       "Model and Methods": a fixed velocity enters along the inflow border,
       the lateral borders are periodic); see `open_borders`.
     """

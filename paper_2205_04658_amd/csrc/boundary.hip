@@ -1,5 +1,5 @@
 // Open x borders and the current-density diagnostics of the channel-flow
-// workload (Ch. 6, "Model and Methods": a fixed velocity enters along the
+// workload (Ch. 5, "Model and Methods": a fixed velocity enters along the
 // inflow border, lateral borders are periodic; the current density is
 // recorded at the outflow border over time and along the channel, and its
 // fluctuations are examined in frequency and wave-number space).

@@ -27,7 +27,7 @@
 
 namespace rlb {
 
-// Open x borders of the new state, set by the waves that hold them (Ch. 6,
+// Open x borders of the new state, set by the waves that hold them (Ch. 5,
 // "Model and Methods": a fixed velocity enters along the inflow border):
 //   * velocity inlet, column 0: equilibrium at the prescribed 3-velocity and
 //     charge density, with the energy density of column 1;

@@ -36,7 +36,7 @@ ADJOINT = dict(nx=512, ny=256, fraction=0.05, radius=6.0, seed=7, tau=0.8,
                body_force=1e-6, steps=2000, checkpoint=100, eps=1.0, n=0.1,
                nmodes=32, kmin=7.0, kmax=9.0, mode_amplitude=1e-6)
 
-# Part II channel (Ch. 6 "Model and Methods"): a 40 x 10 um sample on a
+# Part II channel (Ch. 5 "Model and Methods"): a 40 x 10 um sample on a
 # 1024 x 256 lattice (spacing 0.038 um), flow entering at 0.1 v_F (lattice
 # speed 1 = v_F) through the inlet column, periodic lateral borders, one or
 # two rigid impurities of diameter 0.5 um (radius 0.25 / 0.038 nodes) in the

@@ -1,4 +1,4 @@
-"""Open x borders (Ch. 6, "Model and Methods": a fixed velocity enters along
+"""Open x borders (Ch. 5, "Model and Methods": a fixed velocity enters along
 the inflow border, the lateral borders are periodic) and the current-density
 spectra, pinned by:
 
