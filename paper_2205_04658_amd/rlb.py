@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librlb.so")
+# RLB_LIB_PATH names another build of the same library (the host-sanitizer
+# build of the CPU boundary tests); by default the in-tree librlb.so
+LIB_PATH = os.environ.get("RLB_LIB_PATH") or os.path.join(_HERE, "librlb.so")
 
 OK, EINVAL, EDEVICE, ENOMEM, ENONFINITE, ELANDAU, ESTATE, EUNSUPPORTED = range(8)
 STATUS_NAMES = ["RLB_OK", "RLB_EINVAL", "RLB_EDEVICE", "RLB_ENOMEM", "RLB_ENONFINITE",
