@@ -13,6 +13,9 @@ size: its gradient along a random direction against a central difference
 of its own forward objective, and invariance under the checkpoint
 interval.  The widest rows the library accepts are sampled the same way
 (column offsets at the top of their 32-bit range)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -241,11 +244,18 @@ def test_batched_channels_step_sampled():
     assert worst[0] < TOL and worst[1] < TOL, worst
 
 
-def test_adjoint_full_size_directional_derivative():
-    """512 x 256 channel, 2000 steps, checkpoints every 100, 32 modes: the
-    adjoint gradient along a random direction d equals the central
-    difference (J(theta + h d) - J(theta - h d)) / 2h of the forward
-    objective to 1e-3, and the gradient does not depend on the checkpoint
+ADJOINT512 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "adjoint512_oracle.json")
+
+
+@pytest.mark.parametrize("kind", ["current", "dissipation"])
+def test_adjoint_full_size_directional_derivative(kind):
+    """512 x 256 channel, 2000 steps, checkpoints every 100, 32 modes, both
+    objectives: the adjoint gradient along a seeded direction d equals the
+    central difference (J(theta + h d) - J(theta - h d)) / 2h of the
+    forward objective to 1e-3, and that of the FP64 oracle's runs (stored
+    by tests/golden/make_golden.py) to 1e-3; the objective matches the
+    oracle's to 1e-5; the gradient does not depend on the checkpoint
     interval."""
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import Lattice
@@ -260,7 +270,7 @@ def test_adjoint_full_size_directional_derivative():
         f = workloads.uniform(nx, ny, c["eps"], c["n"])
         lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
         lat.add_disks(discs)
-        return lat.adjoint_run(c["steps"], K, "current", modes, a, fb, grad=grad)
+        return lat.adjoint_run(c["steps"], K, kind, modes, a, fb, grad=grad)
 
     J, g = run(c["body_force"], c["tau"], amps)
     J2, g2 = run(c["body_force"], c["tau"], amps, K=40)
@@ -273,5 +283,11 @@ def test_adjoint_full_size_directional_derivative():
     Jm, _ = run(*(lambda t: (t[0], t[1], t[2:]))(theta - h * d), grad=False)
     fd = (Jp - Jm) / (2 * h)
     ad = float(g @ d)
-    print(f"directional derivative: adjoint {ad:.6e}  central difference {fd:.6e}")
+    gold = json.load(open(ADJOINT512))
+    assert gold["config"]["h"] == h and np.allclose(gold["direction"], d, rtol=1e-15, atol=0)
+    ref = gold[kind]
+    print(f"{kind}: directional derivative: adjoint {ad:.9e}  forward difference {fd:.9e}  "
+          f"oracle {ref['directional']:.9e}; J {J:.9e} oracle {ref['J']:.9e}")
     assert abs(ad - fd) < 1e-3 * abs(fd), (ad, fd)
+    assert abs(ad - ref["directional"]) < 1e-3 * abs(ref["directional"]), (ad, ref)
+    assert abs(J - ref["J"]) < 1e-5 * abs(ref["J"]), (J, ref["J"])
