@@ -187,8 +187,9 @@ def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=No
     lat.sync()
     # HIP events around a launch keep the next kernel from starting early
     # (about 6 us per step at 4096^2 when every launch is timed): the step
-    # kernel of every 8th step is timed, inside the same timed window
-    lat.timing(True, every=8)
+    # kernel of every 8th step is timed, inside the same timed window (every
+    # step's in windows shorter than 64 steps)
+    lat.timing(True, every=8 if steps >= 64 else 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat.step(steps)
