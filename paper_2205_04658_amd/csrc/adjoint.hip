@@ -105,13 +105,25 @@ __device__ __forceinline__ Pi pi_of(const Moments& m, const Frame& fr) {
   return q;
 }
 
+// Tiles of 64 x 4 nodes, ordered as the step kernel orders them: the eight
+// XCDs (workgroup i runs on XCD i mod 8) each take a contiguous band of
+// tiles, visited in vertical strips `strip` tiles wide and row by row
+// inside a strip, so that neighbouring tiles, which share halo rows, meet in
+// one L2.  (Row-major order over the XCDs in turn: 1.31x the algorithmic
+// reads at 512 x 256.)
 template <class DS, bool UNIT, bool MASK>
 __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   constexpr int Q = DS::Q;
-  const int tile = blockIdx.x;
-  if (tile >= a.ntiles) return;
-  const int ty = tile / a.tiles_x;
-  const int x = (tile - ty * a.tiles_x) * 64 + (threadIdx.x & 63);
+  const int t = (int)(blockIdx.x & 7) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+  if (t >= a.ntiles) return;
+  const int tiles_y = (a.ny + 3) / 4;
+  const int sw = min(a.strip, a.tiles_x);
+  const int full = a.tiles_x / sw;
+  const int st = t / (sw * tiles_y);
+  const int w = st < full ? sw : a.tiles_x - full * sw;
+  const int in = t - st * sw * tiles_y;
+  const int ty = in / w;
+  const int x = (st * sw + (in - ty * w)) * 64 + (threadIdx.x & 63);
   const int y = __builtin_amdgcn_readfirstlane(ty * 4 + (threadIdx.x >> 6));
   if (x >= a.nx || y >= a.ny) return;
   const uint32_t node = (uint32_t)(y * a.nx + x);
@@ -476,10 +488,11 @@ __global__ __launch_bounds__(256) void fill_f64_kernel(double* p, size_t n) {
 // ---------------------------------------------------------------------------
 template <class DS, bool UNIT>
 static void adj_go(bool mask, const AdjArgs& a, hipStream_t s) {
+  const dim3 grid(8 * a.tiles_per_xcd);
   if (mask)
-    hipLaunchKernelGGL((adjoint_kernel<DS, UNIT, true>), dim3(a.ntiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((adjoint_kernel<DS, UNIT, true>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((adjoint_kernel<DS, UNIT, false>), dim3(a.ntiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((adjoint_kernel<DS, UNIT, false>), grid, dim3(256), 0, s, a);
 }
 
 hipError_t launch_adjoint(int Q, bool unit, bool mask, const AdjArgs& a, hipStream_t s) {

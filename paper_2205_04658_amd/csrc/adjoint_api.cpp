@@ -26,6 +26,7 @@ namespace {
 constexpr int kObjBlocks = 512;
 constexpr int kGradCols = 256;
 constexpr int kMaxModesAdj = 64;
+constexpr int kAdjStrip = 16;   // adjoint-kernel tile order: strips of 16 tiles (1024 nodes)
 
 rlb_status afail(rlb_status s, const char* fmt, ...) {
   char buf[512];
@@ -274,6 +275,8 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
     aa.row = lat->row;
     aa.tiles_x = (nx + 63) / 64;
     aa.ntiles = aa.tiles_x * ((ny + 3) / 4);
+    aa.tiles_per_xcd = (aa.ntiles + 7) / 8;
+    aa.strip = kAdjStrip;
     aa.kind = cfg->objective;
     int cm = 0;
     // t = N: mu_N = dJ_N / dF~ only
@@ -376,6 +379,8 @@ rlb_status rlb_adjoint_apply(rlb_lattice* lat, int32_t op, const float* d_state,
   aa.row = lat->row;
   aa.tiles_x = (lat->p.nx + 63) / 64;
   aa.ntiles = aa.tiles_x * ((lat->p.ny + 3) / 4);
+  aa.tiles_per_xcd = (aa.ntiles + 7) / 8;
+  aa.strip = kAdjStrip;
   aa.obj_c = 0.0f;
   aa.kind = 0;
   AHIP(launch_adjoint(lat->Q, unit, lat->any_solid, aa, lat->stream), "adjoint");

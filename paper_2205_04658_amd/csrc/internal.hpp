@@ -129,6 +129,8 @@ struct AdjArgs {
   double* acc_itau;       // per-node sum of dJ/d(1/tau)
   int64_t pitch;
   int32_t nx, ny, row, tiles_x, ntiles;
+  int32_t tiles_per_xcd;  // ceil(ntiles / 8): the grid is 8 * tiles_per_xcd
+  int32_t strip;          // tile-order strip width in tiles (as TileArgs)
   float obj_c;            // weight of J_t (0 outside the averaging window)
   int32_t kind;           // 0 current, 1 dissipation
 };
