@@ -94,12 +94,12 @@ Workspace layout(const rlb_params* p, int Q, int64_t pitch) {
   w.coef_off = off; off += align_up((size_t)kMaxModes * 4 * sizeof(double));
   w.modes_off = off; off += align_up((size_t)kMaxModes * sizeof(int4));
   w.bins_off = off; off += align_up((size_t)(kMaxK + 2) * sizeof(int32_t));
-  // series coefficients: (kMaxK + 1) / 8 chunks x 2 halves x ny rows x
-  // 2 components x hi | lo, 16 bytes each
+  // series coefficients: (kMaxK + 1) / 8 chunks x 2 halves x 2 components
+  // x hi | lo x ny rows, 16 bytes each
   w.table_off = off; off += align_up((size_t)(kMaxK + 1) / 8 * 2 * p->ny * 4 * sizeof(uint4));
   w.phase_off = off; off += align_up((size_t)p->ny * sizeof(double2));
   w.force_off = off; off += align_up((size_t)2 * pitch * sizeof(float));
-  // twiddles: (kMaxK + 1) / 8 chunks x 2 halves x nx columns x hi | lo
+  // twiddles: (kMaxK + 1) / 8 chunks x 2 halves x hi | lo x nx columns
   w.twiddle_off = off; off += align_up((size_t)(kMaxK + 1) / 8 * 2 * p->nx * 2 * sizeof(uint4));
   w.partial_off = off; off += align_up((size_t)kRedBlocks * 4 * sizeof(double));
   w.desc_off = off; off += align_up(sizeof(LatDesc));

@@ -71,6 +71,11 @@ __device__ __forceinline__ void split16(double v, _Float16& hi, _Float16& lo) {
 // to cos(k th) with Re(prod) and to sin(k th) with -sign(kx) Im(prod).
 // Rows k past K are written as zeros.  (Drawing in this kernel instead of
 // a one-workgroup draw kernel before it: 14.8 -> 12 us per step at 4096^2.)
+// The phase e^{2 pi i ky y / ny} follows ky through the bin by complex
+// multiplication (about n ulp after n modes, far below the float32 force)
+// instead of a phase-table read per mode (11.9 -> 11.6 us at 4096^2; the
+// kernel is latency-bound: without the mode loop and the draws a launch
+// of this grid takes 5.3 us, the draws add 3 us).
 __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a, int64_t fixed_step) {
   __shared__ double s_c[64][4];
   const int y = blockIdx.x * 64 + threadIdx.x;
@@ -87,6 +92,12 @@ __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a, int64_
   const int64_t t = fixed_step >= 0 ? fixed_step : *(CI64*)a.dstep;
   const int j0 = k <= a.K ? bins[k] : 0;
   const int j1 = k <= a.K ? bins[k + 1] : 0;
+  // e^{2 pi i ky y / ny} of the last mode's ky, advanced by w = e^{2 pi i y
+  // / ny} when ky grows by one (the bins hold their modes by ky ascending),
+  // else read from the phase table
+  const double2 w = a.phase[row ? y : 0];
+  double cs = 1.0, sn = 0.0;
+  int kprev = 0;
   for (int jc = j0; jc < j1; jc += 64) {
     const int n = min(64, j1 - jc);
     if ((int)threadIdx.x < n) {
@@ -98,15 +109,21 @@ __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a, int64_
       s_c[threadIdx.x][3] = c[3];
     }
     __syncthreads();
-    // unrolled so that several phase-table reads are in flight at once
-#pragma unroll 4
     for (int jj = 0; jj < n; ++jj) {
       const int j = jc + jj;
       const int md_y = modes[4 * j + 1], md_z = modes[4 * j + 2];
-      // e^{2 pi i ky y / ny} from the phase table, index reduced exactly
-      // (0 <= ky <= 63 and y < ny < 2^24: the product fits 32 bits)
-      const double2 e = a.phase[row ? (unsigned)(md_z * y) % (unsigned)a.ny : 0u];
-      const double cs = e.x, sn = e.y;
+      if (md_z == kprev + 1) {
+        const double c2 = cs * w.x - sn * w.y;
+        sn = cs * w.y + sn * w.x;
+        cs = c2;
+      } else if (md_z != kprev) {
+        // index reduced exactly (0 <= ky <= 63 and y < ny < 2^24: the
+        // product fits 32 bits)
+        const double2 e = a.phase[row ? (unsigned)(md_z * y) % (unsigned)a.ny : 0u];
+        cs = e.x;
+        sn = e.y;
+      }
+      kprev = md_z;
       const double* c = s_c[jj];
       const double pxr = 2.0 * (c[0] * cs - c[1] * sn);
       const double pxi = 2.0 * (c[0] * sn + c[1] * cs);
@@ -124,16 +141,16 @@ __global__ __launch_bounds__(64) void stir_table_kernel(const StirArgs a, int64_
   if (k == 0) bx = by = 0.0;
   const double sc = (double)a.scale;
   const double v[2][2] = {{ax * sc, bx * sc}, {ay * sc, by * sc}};
-  // item (k / 8, (k / 4) % 2, y, component, hi | lo); halves 2 (k % 4), +1
-  _Float16* base = (_Float16*)(a.table + ((size_t)((k >> 3) * 2 + ((k >> 2) & 1)) * a.ny + y) * 4);
+  // items (k / 8, (k / 4) % 2, component, hi | lo, y); halves 2 (k % 4), +1
+  const size_t part = (size_t)((k >> 3) * 2 + ((k >> 2) & 1));
   const int p = 2 * (k & 3);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     _Float16 h0, l0, h1, l1;
     split16(v[c][0], h0, l0);
     split16(v[c][1], h1, l1);
-    _Float16* hi = base + 8 * (2 * c);
-    _Float16* lo = base + 8 * (2 * c + 1);
+    _Float16* hi = (_Float16*)(a.table + (part * 4 + 2 * c) * a.ny + y);
+    _Float16* lo = (_Float16*)(a.table + (part * 4 + 2 * c + 1) * a.ny + y);
     hi[p] = h0; hi[p + 1] = h1;
     lo[p] = l0; lo[p + 1] = l1;
   }
@@ -148,13 +165,16 @@ __global__ __launch_bounds__(256) void twiddle_kernel(uint4* tw, int K, int nx) 
   const int k = i / nx, x = i - k * nx;
   double sn = 0.0, cs = 0.0;
   if (k <= K) sincospi(2.0 * (double)(((long long)k * x) % nx) / (double)nx, &sn, &cs);
-  _Float16* base = (_Float16*)(tw + ((size_t)((k >> 3) * 2 + ((k >> 2) & 1)) * nx + x) * 2);
+  // items (k / 8, (k / 4) % 2, hi | lo, x); halves 2 (k % 4), +1
+  const size_t part = (size_t)((k >> 3) * 2 + ((k >> 2) & 1));
+  _Float16* hi = (_Float16*)(tw + (part * 2) * nx + x);
+  _Float16* lo = (_Float16*)(tw + (part * 2 + 1) * nx + x);
   const int p = 2 * (k & 3);
   _Float16 hc, lc, hs, ls;
   split16(cs, hc, lc);
   split16(sn, hs, ls);
-  base[p] = hc; base[p + 1] = hs;
-  base[8 + p] = lc; base[8 + p + 1] = ls;
+  hi[p] = hc; hi[p + 1] = hs;
+  lo[p] = lc; lo[p + 1] = ls;
 }
 
 constexpr int kSynthBlocks = 2;                  // 32-column blocks per wavefront
@@ -173,19 +193,29 @@ static inline int synth_chunks(int K) { return (K + 8) >> 3; }
 // Rows and columns past the lattice are clamped on load and skipped on
 // store.  The kernel advances the device step counter when `advance` is set
 // (the series kernel of the next step reads it).
-// Measured at 4096^2 against this form (36 us): 16-byte stores through a
-// per-wavefront LDS tile, the same; the transposed product with 16-byte
-// stores straight from the accumulators (32-byte pieces per row), 148 us;
-// 32 x 32 tiles (6 waves per SIMD), 49 us; 32 x 128 tiles (1 wave per
-// SIMD), 41 us.
+// At 4096^2 the kernel takes 33 us; the same launch with the products
+// but no stores takes 25 us, with the stores but no products 26.5 us (a
+// plain 16-byte-store kernel writes the 134 MB in 22.8 us).  Waiting for
+// each chunk's operands before its products cost 3 us of that (36 us);
+// the operand layout with rows (columns) contiguous, 1 us.  Measured
+// against the 36 us form: 16-byte stores through a per-wavefront LDS
+// tile, the same; the transposed product with 16-byte stores straight
+// from the accumulators (32-byte pieces per row), 148 us; 32 x 32 tiles
+// (6 waves per SIMD), 49 us; 32 x 128 tiles (1 wave per SIMD), 41 us.
+// Keeping each XCD on its own row bands (below; an XCD's L2 then holds
+// an eighth of the series table) measured the same, and is kept.
 __global__ __launch_bounds__(64 * kSynthWaves) void stir_synth_kernel(
     const uint4* __restrict__ table, const uint4* __restrict__ tw, float* __restrict__ force,
     int64_t force_pitch, int nchunks, int nx, int ny, int row_pitch, float inv_scale,
-    int64_t* dstep, int advance) {
+    int64_t* dstep, int advance, int wgs_per_xcd) {
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5, l32 = lane & 31;
   const int tiles_x = (nx + kSynthWaveCols - 1) / kSynthWaveCols;
-  const int tile = blockIdx.x * kSynthWaves + (threadIdx.x >> 6);
+  // workgroups go to the XCDs in turn (blockIdx % 8): give each XCD a
+  // contiguous run of tiles, i.e. of row bands, so that its L2 holds only
+  // its rows' series coefficients besides the twiddles
+  const int wg = (int)(blockIdx.x & 7) * wgs_per_xcd + (int)(blockIdx.x >> 3);
+  const int tile = wg * kSynthWaves + (threadIdx.x >> 6);
   if (advance && tile == 0 && lane == 0) *dstep += 1;
   const int ty = tile / tiles_x;
   const int y0 = ty * 32;
@@ -201,28 +231,53 @@ __global__ __launch_bounds__(64 * kSynthWaves) void stir_synth_kernel(
 #pragma unroll
     for (int i = 0; i < 16; ++i) { acc[0][b][i] = 0.0f; acc[1][b][i] = 0.0f; }
   }
-  for (int c = 0; c < nchunks; ++c) {
+  // operands of one chunk; chunk c + 1's are loaded before chunk c's
+  // products run, so that one L2 round trip per wavefront is waited for
+  // instead of one per chunk
+  struct Ops { uint4 a[4], bh[kSynthBlocks], bl[kSynthBlocks]; };
+  auto load = [&](int c, Ops& o) {
     const size_t part = (size_t)(2 * c + half);
-    const uint4* ap = table + (part * ny + ya) * 4;
-    const half8 axh = __builtin_bit_cast(half8, ap[0]), axl = __builtin_bit_cast(half8, ap[1]);
-    const half8 ayh = __builtin_bit_cast(half8, ap[2]), ayl = __builtin_bit_cast(half8, ap[3]);
-    half8 bh[kSynthBlocks], bl[kSynthBlocks];
+    const uint4* ap = table + part * 4 * ny + ya;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o.a[i] = ap[i * ny];
 #pragma unroll
     for (int b = 0; b < kSynthBlocks; ++b) {
-      const uint4* bp = tw + (part * nx + xb[b]) * 2;
-      bh[b] = __builtin_bit_cast(half8, bp[0]);
-      bl[b] = __builtin_bit_cast(half8, bp[1]);
+      const uint4* bp = tw + part * 2 * nx + xb[b];
+      o.bh[b] = bp[0];
+      o.bl[b] = bp[nx];
     }
+  };
+  auto mma = [&](const Ops& o) {
+    const half8 axh = __builtin_bit_cast(half8, o.a[0]), axl = __builtin_bit_cast(half8, o.a[1]);
+    const half8 ayh = __builtin_bit_cast(half8, o.a[2]), ayl = __builtin_bit_cast(half8, o.a[3]);
 #pragma unroll
     for (int b = 0; b < kSynthBlocks; ++b) {
-      acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(axl, bh[b], acc[0][b], 0, 0, 0);
-      acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(axh, bl[b], acc[0][b], 0, 0, 0);
-      acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(axh, bh[b], acc[0][b], 0, 0, 0);
-      acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ayl, bh[b], acc[1][b], 0, 0, 0);
-      acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ayh, bl[b], acc[1][b], 0, 0, 0);
-      acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ayh, bh[b], acc[1][b], 0, 0, 0);
+      const half8 bh = __builtin_bit_cast(half8, o.bh[b]), bl = __builtin_bit_cast(half8, o.bl[b]);
+      acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(axl, bh, acc[0][b], 0, 0, 0);
+      acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(axh, bl, acc[0][b], 0, 0, 0);
+      acc[0][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(axh, bh, acc[0][b], 0, 0, 0);
+      acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ayl, bh, acc[1][b], 0, 0, 0);
+      acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ayh, bl, acc[1][b], 0, 0, 0);
+      acc[1][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ayh, bh, acc[1][b], 0, 0, 0);
     }
+  };
+  // even and odd chunks; no branch inside the loop, so that the wait
+  // before each product covers only that chunk's loads (the last even load
+  // of an even count reads chunk nchunks - 1 again, unused)
+  Ops o0, o1;
+  load(0, o0);
+  int c = 0;
+  for (; c + 1 < nchunks; c += 2) {   // wave-uniform
+    load(c + 1, o1);
+    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the products
+    mma(o0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(min(c + 2, nchunks - 1), o0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(o1);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  if (c < nchunks) mma(o0);
   // store block by block (the barriers keep one block's accumulators in
   // flight to memory at a time); non-temporal, like the step's stores:
   // measured 7 us less for the step kernel that reads the planes next, at
@@ -280,9 +335,11 @@ hipError_t launch_stir_table(const StirArgs& a, int64_t fixed_step, hipStream_t 
 
 hipError_t launch_stir_synth(const StirArgs& a, bool advance, hipStream_t s) {
   const int tiles = ((a.nx + kSynthWaveCols - 1) / kSynthWaveCols) * ((a.ny + 31) / 32);
-  hipLaunchKernelGGL(stir_synth_kernel, dim3((tiles + kSynthWaves - 1) / kSynthWaves),
-                     dim3(64 * kSynthWaves), 0, s, a.table, a.twiddle, a.force, a.force_pitch,
-                     synth_chunks(a.K), a.nx, a.ny, a.row, a.inv_scale, a.dstep, advance ? 1 : 0);
+  const int wgs = (tiles + kSynthWaves - 1) / kSynthWaves;
+  const int per_xcd = (wgs + 7) / 8;   // tiles past the last one return at once
+  hipLaunchKernelGGL(stir_synth_kernel, dim3(8 * per_xcd), dim3(64 * kSynthWaves), 0, s, a.table,
+                     a.twiddle, a.force, a.force_pitch, synth_chunks(a.K), a.nx, a.ny, a.row,
+                     a.inv_scale, a.dstep, advance ? 1 : 0, per_xcd);
   return hipGetLastError();
 }
 

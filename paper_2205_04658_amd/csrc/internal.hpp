@@ -100,12 +100,13 @@ struct StirArgs {
   double* coef;           // [nmodes][4] (Re Fx, Im Fx, Re Fy, Im Fy)
   // series coefficients (a_k, b_k) of F^x, F^y times `scale`, as float16
   // hi + lo pairs in matrix-operand order: 16-byte items
-  // [k / 8][(k / 4) % 2][ny][component][hi | lo] of 8 halves
-  // (a_k, b_k for 4 consecutive k), zero past K
+  // [k / 8][(k / 4) % 2][component][hi | lo][ny] of 8 halves
+  // (a_k, b_k for 4 consecutive k), zero past K: consecutive rows are
+  // consecutive items, so the synthesis's operand loads are contiguous
   uint4* table;
   const double2* phase;   // [ny] (cos, sin)(2 pi m / ny)
   // (cos, sin)(2 pi k x / nx) as float16 hi + lo pairs: 16-byte items
-  // [k / 8][(k / 4) % 2][nx][hi | lo] of 8 halves, zero past K
+  // [k / 8][(k / 4) % 2][hi | lo][nx] of 8 halves, zero past K
   const uint4* twiddle;
   float scale, inv_scale; // power of two keeping the coefficients in float16's normal range
   float* force;           // [2][force_pitch] synthesised force planes, rows padded
