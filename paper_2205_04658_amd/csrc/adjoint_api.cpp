@@ -7,7 +7,9 @@
 // the lattice stream while the adjoint sweeps segment s on a second stream
 // (both are latency-bound on channel-sized lattices).  Events order the
 // buffer reuse; the adjoint kernels keep one stream and one order, so the
-// gradient is the same bit for bit.
+// gradient is the same bit for bit.  The forward pass steps the last
+// segments (one per buffer) inside the buffers themselves, so the sweep
+// starts at once and those segments are never recomputed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -104,7 +106,9 @@ AdjLayout adj_layout(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
   L.modes_off = off; off += align_up(kMaxModesAdj * 6 * sizeof(double));
   L.partial_off = off; off += align_up((size_t)(2 + kMaxModesAdj) * kGradCols * sizeof(double));
   L.result_off = off; off += align_up(128 * sizeof(double));
-  L.desc_off = off; off += align_up(sizeof(LatDesc) * (size_t)K * (size_t)L.nbuf);
+  // recompute descriptors, then per buffer the two exits of a forward
+  // segment stepped in the buffer (its last state -> lattice copy 0 | 1)
+  L.desc_off = off; off += align_up(sizeof(LatDesc) * ((size_t)K + 2) * (size_t)L.nbuf);
   L.total = off;
   return L;
 }
@@ -185,8 +189,12 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
   StepShared sh = shared_of(lat);
   const bool unit = lat->p.cfl == 1.0, mask = lat->any_solid;
 
-  // recompute descriptors of buffer b: store(b, j) -> store(b, j + 1)
-  std::vector<LatDesc> hd((size_t)(K * L.nbuf));
+  // recompute descriptors of buffer b: store(b, j) -> store(b, j + 1); then
+  // the exits of the segments the forward pass steps in the buffers (the
+  // last nbuf, one per buffer, when a gradient is asked for): exit(b, c) is
+  // store(b, len - 1) -> lattice copy c
+  const int64_t kept_from = h_grad ? L.nseg - L.nbuf : L.nseg;
+  std::vector<LatDesc> hd((size_t)((K + 2) * L.nbuf));
   for (int64_t b = 0; b < L.nbuf; ++b)
     for (int64_t j = 0; j < K; ++j) {
       LatDesc d = lat->desc;
@@ -194,6 +202,15 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
       d.state[1] = store(b, std::min<int64_t>(j + 1, K - 1));
       hd[(size_t)(b * K + j)] = d;
     }
+  for (int64_t seg = kept_from; seg < L.nseg; ++seg) {
+    const int64_t b = seg % L.nbuf, len = std::min<int64_t>(K, N - seg * K);
+    for (int c = 0; c < 2; ++c) {
+      LatDesc d = lat->desc;
+      d.state[0] = store(b, len - 1);
+      d.state[1] = lat->state[c];
+      hd[(size_t)(K * L.nbuf + 2 * b + c)] = d;
+    }
+  }
   AHIP(hipMemcpyAsync(d_desc, hd.data(), sizeof(LatDesc) * hd.size(), hipMemcpyHostToDevice, st),
        "descriptors");
   AHIP(hipStreamSynchronize(st), "stream synchronize");
@@ -226,17 +243,42 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
 
   // ---- forward with checkpoints ----
   // J_t of the states s_t, N/2 < t < N, is summed by the step kernel that
-  // streams s_t (MODE_OBJ, per-wavefront slots); s_N by the objective kernel
+  // streams s_t (MODE_OBJ, per-wavefront slots); s_N by the objective kernel.
+  // Segments from kept_from on run in their recompute buffers: s_t0 copied
+  // in, s_t0+j -> s_t0+j+1 inside the buffer, the last state out to the
+  // lattice's other copy.
+  TileArgs tf;
+  tf.sh = sh;
+  tf.sh.obj = obj_slots;
+  tf.sh.obj_kind = cfg->objective;
+  tf.tile_lat = nullptr;
+  tf.parity = 0;
+  tf.tile_first = 0;
+  tf.ntiles = tiles_of(nx, ny, lat->Q == 17 ? lat->shape.tile_rows : 4);
+  tf.fields = nullptr;
   for (int64_t t = 0; t < N; ++t) {
-    if (t % K == 0)
-      AHIP(hipMemcpyAsync(ck(t / K), lat->state[lat->cur], state_copy, hipMemcpyDeviceToDevice, st),
-           "checkpoint");
-    if (t > N / 2)
-      AHIP(launch_step(lat, MODE_OBJ, FORCE_STIR, lat->cur, nullptr, 0, nullptr, 0, obj_slots,
-                       cfg->objective), "step");
-    else
-      AHIP(launch_step(lat, MODE_STEP, FORCE_STIR, lat->cur, nullptr, 0), "step");
-    lat->cur ^= 1;
+    const int64_t seg = t / K, j = t - seg * K;
+    if (seg < kept_from) {
+      if (j == 0)
+        AHIP(hipMemcpyAsync(ck(seg), lat->state[lat->cur], state_copy, hipMemcpyDeviceToDevice, st),
+             "checkpoint");
+      if (t > N / 2)
+        AHIP(launch_step(lat, MODE_OBJ, FORCE_STIR, lat->cur, nullptr, 0, nullptr, 0, obj_slots,
+                         cfg->objective), "step");
+      else
+        AHIP(launch_step(lat, MODE_STEP, FORCE_STIR, lat->cur, nullptr, 0), "step");
+      lat->cur ^= 1;
+    } else {
+      const int64_t b = seg % L.nbuf, len = std::min<int64_t>(K, N - seg * K);
+      if (j == 0)
+        AHIP(hipMemcpyAsync(store(b, 0), lat->state[lat->cur], state_copy, hipMemcpyDeviceToDevice, st),
+             "segment start");
+      const bool last = j + 1 == len;
+      tf.lats = last ? d_desc + K * L.nbuf + 2 * b + (lat->cur ^ 1) : d_desc + b * K + j;
+      AHIP(launch_tiles(lat->Q, stream_mode(lat->p.cfl), mask, t > N / 2 ? MODE_OBJ : MODE_STEP,
+                        FORCE_STIR, tf, lat->shape, lat->num_cu, st), "step");
+      if (last) lat->cur ^= 1;
+    }
     lat->step += 1;
   }
   oa.state = lat->state[lat->cur];
@@ -305,7 +347,12 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
       AHIP(hipEventRecord(ev_rec, st), "event record");
       return RLB_OK;
     };
-    if (rlb_status s = recompute(L.nseg - 1)) return s;
+    // segments from kept_from on are in their buffers already
+    if (kept_from > L.nseg - 1) {
+      if (rlb_status s = recompute(L.nseg - 1)) return s;
+    } else {
+      AHIP(hipEventRecord(ev_rec, st), "event record");
+    }
     for (int64_t seg = L.nseg - 1; seg >= 0; --seg) {
       const int64_t t0 = seg * K, len = std::min<int64_t>(K, N - t0), b = seg % L.nbuf;
       AHIP(hipStreamWaitEvent(sa, ev_rec, 0), "stream wait");   // segment seg recomputed
@@ -322,7 +369,9 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
         // the buffer of segment seg - 1 was last read by the sweep of seg + 1
         // (nbuf is 2 whenever there is more than one segment)
         if (seg + 1 < L.nseg) AHIP(hipStreamWaitEvent(st, ev_adj[(seg + 1) & 1], 0), "stream wait");
-        if (rlb_status s = recompute(seg - 1)) return s;
+        if (seg - 1 < kept_from) {
+          if (rlb_status s = recompute(seg - 1)) return s;
+        }
       }
     }
     AHIP(hipEventRecord(ev_join, sa), "event record");

@@ -74,6 +74,12 @@ def test_forward_only_matches_and_advances():
     lat2 = gpu_lattice()
     J1, _ = lat2.adjoint_run(N, 10, "current", MODES, AMPS, FB)
     assert J0 == J1
+    # with a gradient the forward pass steps its last segments inside the
+    # recompute buffers; the lattice still ends at the same state s_N
+    assert lat2.step_count == N
+    f0, f1 = lat.fields(), lat2.fields()
+    for k in f0:
+        assert torch.equal(f0[k], f1[k]), k
 
 
 def test_autograd_function():
