@@ -199,11 +199,13 @@ def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=No
     kms, launches = lat.timing_read()
     lat.timing(False)
     lat.sync()
-    # totals over the timed steps: the charge is conserved, and so is the
-    # momentum (the stirring shell has no k = 0 mode; its change is given
-    # relative to the energy); the energy grows by the stirring's work.
-    # The totals kernel also reads every population once, which the
-    # counter summaries use to check their calibration
+    # totals over the timed steps: the charge is conserved; energy and
+    # momentum change by the stirring's work and impulse (its driving term
+    # scales with the local energy density, so a zero-mean force field on a
+    # non-uniform flow still moves the total momentum; the change is given
+    # relative to the energy).  The totals kernel also reads every
+    # population once, which the counter summaries use to check their
+    # calibration
     tot1 = lat.conserved()
     drift = dict(steps=steps, energy=float((tot1[0] - tot0[0]) / tot0[0]),
                  charge=float((tot1[3] - tot0[3]) / tot0[3]),
