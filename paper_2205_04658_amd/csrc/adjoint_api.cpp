@@ -254,7 +254,6 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
   tf.tile_lat = nullptr;
   tf.parity = 0;
   tf.tile_first = 0;
-  tf.ntiles = tiles_of(nx, ny, lat->Q == 17 ? lat->shape.tile_rows : 4);
   tf.fields = nullptr;
   for (int64_t t = 0; t < N; ++t) {
     const int64_t seg = t / K, j = t - seg * K;
@@ -274,9 +273,11 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
         AHIP(hipMemcpyAsync(store(b, 0), lat->state[lat->cur], state_copy, hipMemcpyDeviceToDevice, st),
              "segment start");
       const bool last = j + 1 == len;
+      const int md = t > N / 2 ? MODE_OBJ : MODE_STEP;
       tf.lats = last ? d_desc + K * L.nbuf + 2 * b + (lat->cur ^ 1) : d_desc + b * K + j;
-      AHIP(launch_tiles(lat->Q, stream_mode(lat->p.cfl), mask, t > N / 2 ? MODE_OBJ : MODE_STEP,
-                        FORCE_STIR, tf, lat->shape, lat->num_cu, st), "step");
+      tf.ntiles = tiles_of(nx, ny, kernel_tile_rows(lat->Q, md, lat->shape.tile_rows));
+      AHIP(launch_tiles(lat->Q, stream_mode(lat->p.cfl), mask, md, FORCE_STIR, tf, lat->shape,
+                        lat->num_cu, st), "step");
       if (last) lat->cur ^= 1;
     }
     lat->step += 1;
@@ -332,7 +333,7 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
     ta.tile_lat = nullptr;
     ta.parity = 0;
     ta.tile_first = 0;
-    ta.ntiles = tiles_of(nx, ny, lat->Q == 17 ? lat->shape.tile_rows : 4);
+    ta.ntiles = tiles_of(nx, ny, kernel_tile_rows(lat->Q, MODE_STEP, lat->shape.tile_rows));
     ta.fields = nullptr;
     // restore segment seg's checkpoint into buffer seg % nbuf and recompute
     // its states on the lattice stream

@@ -930,8 +930,8 @@ rlb_status rlb_set_launch_shape(rlb_lattice* lat, int32_t tile_rows, int32_t gri
   if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: use the batch's launch shape (rlb_batch_set_launch_shape)");
   if (!(tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8))
     return fail(RLB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
-  if (lat->Q != 17 && tile_rows != 4)
-    return fail(RLB_EUNSUPPORTED, "tile_rows != 4 needs the folded layout");
+  if (lat->Q != 17 && tile_rows != 4 && !(lat->Q == 26 && tile_rows == 2))
+    return fail(RLB_EUNSUPPORTED, "tile_rows 1 and 8 need the folded layout, 2 the folded or the full one");
   if (grid_per_cu < 0 || grid_per_cu > 64) return fail(RLB_EINVAL, "grid_per_cu must be in [0, 64]");
   if (strip < 1 || strip > 65536) return fail(RLB_EINVAL, "strip must be in [1, 65536]");
   lat->shape = LaunchShape{tile_rows, grid_per_cu, strip};
@@ -960,7 +960,7 @@ rlb_status rlb_autotune(rlb_lattice* lat, int32_t trials, double* h_ms, int32_t 
     }
     return hipSuccess;
   };
-  const std::vector<LaunchShape> cand = launch_candidates(lat->Q);
+  const std::vector<LaunchShape> cand = launch_candidates(lat->Q, false);
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "event");
   HIP_TRY(hipEventCreate(&e1), "event");

@@ -514,7 +514,7 @@ rlb_status rlb_batch_autotune(rlb_batch* B, int32_t trials, double* h_ms, int32_
   const bool mask = any_solid(B);
   const int force = force_mode(B);
   drop_graph(B);
-  const std::vector<LaunchShape> cand = launch_candidates(B->Q);
+  const std::vector<LaunchShape> cand = launch_candidates(B->Q, true);
   hipEvent_t e0, e1;
   BHIP(hipEventCreate(&e0), "event");
   BHIP(hipEventCreate(&e1), "event");

@@ -247,9 +247,15 @@ hipError_t launch_tiles(int Q, int sm, bool mask, int mode, int force_mode,
                         const TileArgs& a, LaunchShape shape, int num_cu,
                         hipStream_t s);
 int tiles_of(int nx, int ny, int tile_rows);
-// Launch shapes the autotuners time (tile heights other than 4 only for the
-// folded set).
-std::vector<LaunchShape> launch_candidates(int Q);
+// The tile height the step kernels of a launch use for a shape's tile_rows:
+// any of 1, 2, 4, 8 for the folded set (field read-out: 4), 2 or 4 for the
+// full set's step (MODE_STEP), 4 otherwise.  Tile counts (tiles_of) must be
+// taken with this height.
+int kernel_tile_rows(int Q, int mode, int tile_rows);
+// Launch shapes the autotuners time: tile heights 1, 2, 4, 8 for the folded
+// set, 2 and 4 for a single full-set lattice, 4 otherwise (batches of the
+// full set included).
+std::vector<LaunchShape> launch_candidates(int Q, bool batch);
 hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode,
                        int parity, float* fields, uint32_t field_mask,
                        double* rec = nullptr, int rec_x = 0, double* obj = nullptr,

@@ -518,12 +518,19 @@ int tiles_of(int nx, int ny, int tile_rows) {
   return ((nx + 63) / 64) * ((ny + tile_rows - 1) / tile_rows);
 }
 
-std::vector<LaunchShape> launch_candidates(int Q) {
+int kernel_tile_rows(int Q, int mode, int tile_rows) {
+  if (mode == MODE_FIELDS) return 4;
+  if (Q == 17) return tile_rows;
+  if (Q == 26 && mode == MODE_STEP && tile_rows == 2) return 2;
+  return 4;
+}
+
+std::vector<LaunchShape> launch_candidates(int Q, bool batch) {
   std::vector<LaunchShape> c;
   for (int ty : {1, 2, 4, 8})
     for (int g : {0, 4})
       for (int sw : {4, 8, 16, 32})
-        if (Q == 17 || ty == 4) c.push_back(LaunchShape{ty, g, sw});
+        if (Q == 17 || ty == 4 || (Q == 26 && ty == 2 && !batch)) c.push_back(LaunchShape{ty, g, sw});
   return c;
 }
 
@@ -534,7 +541,9 @@ static void go(const TileArgs& a, int grid, hipStream_t s) {
 }
 
 // Tile heights other than 4 are compiled for the folded set's step kernels
-// only (the autotuner's search space); everything else uses 4.
+// and the full set's plain step (2-row tiles: 1.308 -> 1.276 ms at 4096^2
+// stirred; 1 and 8 rows no faster than 4); everything else uses 4.  `ty`
+// comes from kernel_tile_rows, which the tile counts use too.
 template <class DS, int SM, bool MASK, int FORCE, int MODE>
 static void by_rows(int ty, const TileArgs& a, int grid, hipStream_t s) {
   if constexpr (DS::Q == 17 && MODE != MODE_FIELDS) {
@@ -543,6 +552,11 @@ static void by_rows(int ty, const TileArgs& a, int grid, hipStream_t s) {
       case 2: go<DS, SM, MASK, FORCE, MODE, 2>(a, grid, s); return;
       case 8: go<DS, SM, MASK, FORCE, MODE, 8>(a, grid, s); return;
       default: break;
+    }
+  } else if constexpr (DS::Q == 26 && MODE == MODE_STEP) {
+    if (ty == 2) {
+      go<DS, SM, MASK, FORCE, MODE, 2>(a, grid, s);
+      return;
     }
   }
   go<DS, SM, MASK, FORCE, MODE, 4>(a, grid, s);
@@ -599,8 +613,7 @@ hipError_t launch_tiles(int Q, int sm, bool mask, int mode, int force_mode,
                         const TileArgs& a0, LaunchShape shape, int num_cu, hipStream_t s) {
   if (a0.ntiles <= 0) return hipSuccess;
   TileArgs a = a0;
-  int ty = shape.tile_rows;
-  if (!(Q == 17 && mode != MODE_FIELDS)) ty = 4;
+  const int ty = kernel_tile_rows(Q, mode, shape.tile_rows);
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
   a.strip = std::max(1, shape.strip);
   int grid;
@@ -631,7 +644,7 @@ hipError_t launch_step(const rlb_lattice* lat, int mode, int force_mode, int par
   a.tile_lat = nullptr;
   a.parity = parity;
   a.tile_first = 0;
-  const int ty = (mode != MODE_FIELDS && lat->Q == 17) ? lat->shape.tile_rows : 4;
+  const int ty = kernel_tile_rows(lat->Q, mode, lat->shape.tile_rows);
   a.ntiles = tiles_of(lat->p.nx, lat->p.ny, ty);
   a.fields = fields;
   LaunchShape sh = lat->shape;

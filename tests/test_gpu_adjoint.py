@@ -32,9 +32,9 @@ def solid():
     return geometry.channel_mask(NX, NY, DISCS)
 
 
-def gpu_lattice():
+def gpu_lattice(full26=False):
     from paper_2205_04658_amd.rlb import Lattice
-    lat = Lattice(NX, NY, TAU, walls=True)
+    lat = Lattice(NX, NY, TAU, walls=True, full26=full26)
     f = fields()
     lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
     lat.add_disks(DISCS)
@@ -64,6 +64,25 @@ def test_checkpoint_interval_does_not_change_gradient():
     for J, g in out[1:]:
         assert J == out[0][0]
         np.testing.assert_array_equal(g, out[0][1])
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
+def test_tile_height_does_not_change_gradient(full):
+    """The forward, objective and recompute steps may run at different tile
+    heights (the full set's plain step has 2-row tiles, its objective step
+    4-row ones): every launch covers the whole lattice and the gradient,
+    objective and final state are the same bit for bit."""
+    torch = need_gpu()
+    out = []
+    for shape in ((4, 0, 16), (2, 0, 16), (2, 4, 8)):
+        lat = gpu_lattice(full)
+        lat.set_launch_shape(*shape)
+        J, g = lat.adjoint_run(N, 7, "current", MODES, AMPS, FB)
+        out.append((J, g, lat.save_state().cpu()))
+    for J, g, s in out[1:]:
+        assert J == out[0][0]
+        np.testing.assert_array_equal(g, out[0][1])
+        assert torch.equal(s, out[0][2])
 
 
 def test_forward_only_matches_and_advances():

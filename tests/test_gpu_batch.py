@@ -69,16 +69,50 @@ def test_launch_shapes_are_bitwise_identical():
                 assert torch.equal(s, ref), (ty, g, sw)
 
 
-def test_tile_heights_other_than_4_need_the_folded_layout():
+def test_tile_heights_the_layouts_support():
+    """Tile heights 1, 2, 4, 8 for the folded set; 2 and 4 for the full set
+    (its plain step is compiled for both); 4 for the planar set.  A
+    refused shape leaves the current one."""
     need_gpu()
     from paper_2205_04658_amd.rlb import EUNSUPPORTED, Lattice, RLBError
-    for kw in (dict(full26=True), dict(planar=True)):
+    for kw, ok in ((dict(full26=True), (2, 4)), (dict(planar=True), (4,))):
         lat = Lattice(64, 16, 0.7, **kw)
-        lat.set_launch_shape(4, 4, 8)
-        with pytest.raises(RLBError) as e:
-            lat.set_launch_shape(2, 0, 16)
-        assert e.value.status == EUNSUPPORTED
-        assert lat.launch_shape() == (4, 4, 8)
+        for ty in (1, 2, 8):
+            lat.set_launch_shape(4, 4, 8)
+            if ty in ok:
+                lat.set_launch_shape(ty, 0, 16)
+                assert lat.launch_shape() == (ty, 0, 16)
+            else:
+                with pytest.raises(RLBError) as e:
+                    lat.set_launch_shape(ty, 0, 16)
+                assert e.value.status == EUNSUPPORTED
+                assert lat.launch_shape() == (4, 4, 8)
+
+
+def test_full_set_tile_heights_are_bitwise_identical():
+    """The full set's plain step at 2- and 4-row tiles, every grid and strip
+    form, walls + discs + stirring + body force, and the field read-out
+    (always 4-row tiles) after it."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    ref = None
+    for ty in (2, 4):
+        for g in (0, 8):
+            for sw in (1, 3, 16):
+                lat = Lattice(200, 37, 0.7, walls=True, full26=True)
+                lat.set_launch_shape(ty, g, sw)
+                f = workloads.random_fields(200, 37, seed=4)
+                lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+                lat.add_disks([(20.0, 15.0, 5.0), (150.0, 20.0, 4.0)])
+                lat.set_stirring(2, 5, 1e-4, 9)
+                lat.set_body_force(1e-4, 0)
+                lat.step(11)
+                s = lat.save_state().cpu()
+                fl = lat.fields()["eps"].cpu()
+                if ref is None:
+                    ref = (s, fl)
+                assert torch.equal(s, ref[0]), (ty, g, sw)
+                assert torch.equal(fl, ref[1]), (ty, g, sw)
 
 
 @pytest.mark.parametrize("graph", [16, 0], ids=["graph", "direct"])
