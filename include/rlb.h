@@ -196,6 +196,19 @@ rlb_status rlb_read_fields(rlb_lattice* lat, uint32_t field_mask, float* d_out);
  * in float64 in a fixed order (deterministic).  Synchronises. */
 rlb_status rlb_conserved(rlb_lattice* lat, double h_out[4]);
 
+/* Energy and momentum the driving term (Ch. 4 eq. forceTerm, discretised as
+ * in the appendix on the forcing term) adds in the lattice's next step:
+ *   h_out = {sum F.T^{0k} / 6, sum F^x T^{00} / 6, sum F^y T^{00} / 6}
+ * over fluid nodes, with T^{0 mu} from the current state streamed as the
+ * step streams it and F the next step's force (body force + the stirring
+ * field of step rlb_get_step).  On a periodic lattice without obstacles the
+ * totals of rlb_conserved change by exactly these amounts over that step
+ * (up to the float32 rounding of the state).  Summed in float64 in a fixed
+ * order; overwrites the lattice's stirring planes (every step synthesises
+ * its own).  RLB_EUNSUPPORTED for the planar set, RLB_EINVAL for a batch
+ * member.  Synchronises. */
+rlb_status rlb_force_injection(rlb_lattice* lat, double h_out[3]);
+
 /* Wait for queued work; report sticky device failures. */
 rlb_status rlb_sync(rlb_lattice* lat);
 

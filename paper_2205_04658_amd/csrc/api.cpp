@@ -777,6 +777,24 @@ rlb_status rlb_conserved(rlb_lattice* lat, double h_out[4]) {
   return RLB_OK;
 }
 
+rlb_status rlb_force_injection(rlb_lattice* lat, double h_out[3]) {
+  if (rlb_status s = check_lat(lat)) return s;
+  if (!h_out) return fail(RLB_EINVAL, "output is null");
+  if (lat->owner) return fail(RLB_EINVAL, "lattice is a batch member: the batch holds its force");
+  if (lat->Q == 12) return fail(RLB_EUNSUPPORTED, "the planar set has no driving term");
+  if (lat->stir) {   // the next step's stirring field into the force planes
+    const StirArgs a = stir_args(lat);
+    HIP_TRY(launch_stir_table(a, lat->step, lat->stream), "stirring table");
+    HIP_TRY(launch_stir_synth(a, false, lat->stream), "stirring synthesis");
+  }
+  HIP_TRY(launch_injection(lat, lat->stir, lat->result), "injection kernel");
+  double tmp[4];
+  HIP_TRY(hipMemcpyAsync(tmp, lat->result, sizeof tmp, hipMemcpyDeviceToHost, lat->stream), "read injection");
+  if (rlb_status s = read_err(lat)) return s;
+  std::memcpy(h_out, tmp, 3 * sizeof(double));
+  return RLB_OK;
+}
+
 rlb_status rlb_sync(rlb_lattice* lat) {
   if (rlb_status s = check_lat(lat)) return s;
   return read_err(lat);

@@ -327,6 +327,9 @@ hipError_t static_scratch(int device, double** ptr);
 // reduce.hip
 hipError_t launch_totals(const rlb_lattice* lat, const float* state,
                          double* result);
+// Energy and momentum the next step's driving term adds (result[0..2]);
+// the stirring planes must hold the next step's field when `planes`.
+hipError_t launch_injection(const rlb_lattice* lat, bool planes, double* result);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes,
                        hipStream_t s);
 

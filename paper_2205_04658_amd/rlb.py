@@ -28,7 +28,8 @@ FIELDS = ["eps", "beta_x", "beta_y", "n", "T00", "T0x", "T0y", "Txx", "Txy", "Ty
 SYMBOLS = [
     "rlb_workspace_bytes", "rlb_create", "rlb_destroy", "rlb_init_fields",
     "rlb_set_obstacles", "rlb_add_disks", "rlb_clear_obstacles", "rlb_set_body_force",
-    "rlb_set_stirring", "rlb_step", "rlb_use_graph", "rlb_read_fields", "rlb_conserved", "rlb_sync",
+    "rlb_set_stirring", "rlb_step", "rlb_use_graph", "rlb_read_fields", "rlb_conserved",
+    "rlb_force_injection", "rlb_sync",
     "rlb_get_step", "rlb_state_bytes", "rlb_save_state", "rlb_load_state", "rlb_layout",
     "rlb_stirring_coefficients", "rlb_stirring_field", "rlb_philox", "rlb_timing",
     "rlb_timing_read", "rlb_copy_probe", "rlb_last_error", "rlb_version",
@@ -102,6 +103,7 @@ def lib():
         "rlb_use_graph": [_vp, _i32],
         "rlb_read_fields": [_vp, _u32, _vp],
         "rlb_conserved": [_vp, _P(_d)],
+        "rlb_force_injection": [_vp, _P(_d)],
         "rlb_sync": [_vp],
         "rlb_get_step": [_vp, _P(_i64)],
         "rlb_state_bytes": [_vp, _P(_sz)],
@@ -332,6 +334,12 @@ class Lattice:
     def conserved(self):
         out = (_d * 4)()
         check(lib().rlb_conserved(self._h, out))
+        return np.array(out[:])
+
+    def force_injection(self):
+        """(dE, dP^x, dP^y) the next step's driving term adds (rlb_force_injection)."""
+        out = (_d * 3)()
+        check(lib().rlb_force_injection(self._h, out))
         return np.array(out[:])
 
     def layout(self):
