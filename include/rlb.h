@@ -359,8 +359,9 @@ rlb_status rlb_timing(rlb_lattice* lat, int32_t enable);
 rlb_status rlb_timing_read(rlb_lattice* lat, double* total_ms, int64_t* launches);
 
 /* Launch shape of the step kernel: tiles of 64 x tile_rows nodes (one
- * wavefront per row; tile_rows in {1, 2, 4, 8}, other than 4 only for the
- * folded layout, else RLB_EUNSUPPORTED); the grid: grid_per_cu = 0 launches one workgroup per
+ * wavefront per row; tile_rows in {1, 2, 4, 8} for the folded layout, 2 or 4
+ * for RLB_FULL26 (its plain step; its other kernels keep 4), 4 for
+ * RLB_PLANAR, else RLB_EUNSUPPORTED); the grid: grid_per_cu = 0 launches one workgroup per
  * tile, k > 0 launches about k resident workgroups of 4 wavefronts per CU
  * that walk the tile list; and the tile order: a lattice's tiles are
  * visited in vertical strips `strip` tiles wide (1..65536; the last strip
@@ -373,7 +374,8 @@ rlb_status rlb_get_launch_shape(const rlb_lattice* lat, int32_t* tile_rows, int3
                                 int32_t* strip);
 
 /* Autotuner: time `trials` step-kernel launches for every candidate shape
- * (tile_rows x grid_per_cu in {0, 4} x strip in {4, 8, 16, 32}) on the
+ * (the tile_rows the layout accepts x grid_per_cu in {0, 4} x strip in
+ * {4, 8, 16, 32}) on the
  * current state -- each launch reads the current copy and overwrites the
  * other, so the state does not advance -- and keep the fastest.  If h_ms
  * is not null, up to max_results rows (tile_rows, grid_per_cu, strip, ms
@@ -461,9 +463,10 @@ rlb_status rlb_batch_sync(rlb_batch* batch);
 rlb_status rlb_batch_info(const rlb_batch* batch, int32_t* count, int64_t* cells,
                           int32_t* planes, int64_t* step);
 
-/* Launch shape (as rlb_set_launch_shape) and autotuner (as rlb_autotune)
- * of the batched step; graph replay of steps_per_graph (even, 0 = off,
- * default 16) steps per launch. */
+/* Launch shape (as rlb_set_launch_shape, except that a batch of the full
+ * set keeps tile_rows 4) and autotuner (as rlb_autotune) of the batched
+ * step; graph replay of steps_per_graph (even, 0 = off, default 16) steps
+ * per launch. */
 rlb_status rlb_batch_set_launch_shape(rlb_batch* batch, int32_t tile_rows, int32_t grid_per_cu,
                                       int32_t strip);
 rlb_status rlb_batch_get_launch_shape(const rlb_batch* batch, int32_t* tile_rows,
