@@ -17,7 +17,8 @@
 // Landau matching is differentiated implicitly: with A = T g, l = g u,
 //     d eps = u_mu u_nu dT^{mu nu},
 //     [A - eps I, u; l^T, 0] [du; 0] = [d eps u - dA u; 0],
-// so the adjoint solves the transposed 4x4 bordered system once per node.
+// so the adjoint solves the transposed bordered system once per node, as a
+// regular 3x3 system (see the reverse sweep).
 #include <algorithm>
 
 #include "internal.hpp"
@@ -26,38 +27,6 @@
 #include "brick.hpp"
 
 namespace rlb {
-
-// Solve M z = b (4x4, partial pivoting), float64.
-__device__ __forceinline__ void solve4(double M[4][4], double b[4]) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    int piv = c;
-    double best = fabs(M[c][c]);
-#pragma unroll
-    for (int r = c + 1; r < 4; ++r)
-      if (fabs(M[r][c]) > best) { best = fabs(M[r][c]); piv = r; }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (piv != c) { const double t = M[c][k]; M[c][k] = M[piv][k]; M[piv][k] = t; }
-    }
-    if (piv != c) { const double t = b[c]; b[c] = b[piv]; b[piv] = t; }
-    const double inv = 1.0 / M[c][c];
-#pragma unroll
-    for (int r = c + 1; r < 4; ++r) {
-      const double f = M[r][c] * inv;
-#pragma unroll
-      for (int k = c; k < 4; ++k) M[r][k] -= f * M[c][k];
-      b[r] -= f * b[c];
-    }
-  }
-#pragma unroll
-  for (int c = 3; c >= 0; --c) {
-    double v = b[c];
-#pragma unroll
-    for (int k = c + 1; k < 4; ++k) v -= M[c][k] * b[k];
-    b[c] = v / M[c][c];
-  }
-}
 
 struct Moments {
   double T00, T0x, T0y, Txx, Txy, Tyy, J0, Jx, Jy;
@@ -288,25 +257,42 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
     }
   }
 
-  // Landau matching, implicitly: solve [A - eps I, u; l^T, 0]^T [z; zeta] =
-  // [lambda_u; 0], then lambda_T = (lambda_eps + z.u) l l^T - sym(z l^T)
+  // Landau matching, implicitly: solve [B, l; u^T, 0] [z; zeta] =
+  // [lambda_u; 0] with B = (A - eps I)^T, then lambda_T = (lambda_eps + z.u)
+  // l l^T - sym(z l^T).  Since A u = eps u, u^T B = 0, and u.l = u_mu u^mu
+  // = 1: the first three rows dotted with u give zeta = u.lambda_u.  The
+  // rank-one term l u^T fills B's null direction, M = B + l u^T is regular
+  // (at rest its determinant is about -(4 eps / 3)^2), and M z = lambda_u -
+  // zeta l has the solution of the bordered system (u.z = 0 follows from
+  // u^T M z = u.z).  Solved by the adjugate: no pivoting, one division.
   {
     const double u[3] = {fr.u0, fr.ux, fr.uy};
     const double l[3] = {fr.u0, -fr.ux, -fr.uy};
     const double Am[3][3] = {{m.T00, -m.T0x, -m.T0y},
                              {m.T0x, -m.Txx, -m.Txy},
                              {m.T0y, -m.Txy, -m.Tyy}};
-    double K[4][4];
+    double M[3][3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) K[r][c] = Am[c][r] - (r == c ? fr.eps : 0.0);
-      K[r][3] = l[r];
-      K[3][r] = u[r];
+      for (int c = 0; c < 3; ++c) M[r][c] = Am[c][r] - (r == c ? fr.eps : 0.0) + l[r] * u[c];
     }
-    K[3][3] = 0.0;
-    double z[4] = {lU0, lUx, lUy, 0.0};
-    solve4(K, z);
+    const double zeta = u[0] * lU0 + u[1] * lUx + u[2] * lUy;
+    const double rhs[3] = {lU0 - zeta * l[0], lUx - zeta * l[1], lUy - zeta * l[2]};
+    // cofactors C[i][j] of M; M^{-1}[i][j] = C[j][i] / det
+    const double C00 = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    const double C01 = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+    const double C02 = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+    const double C10 = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+    const double C11 = M[0][0] * M[2][2] - M[0][2] * M[2][0];
+    const double C12 = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+    const double C20 = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+    const double C21 = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+    const double C22 = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    const double idet = 1.0 / (M[0][0] * C00 + M[0][1] * C01 + M[0][2] * C02);
+    const double z[3] = {(C00 * rhs[0] + C10 * rhs[1] + C20 * rhs[2]) * idet,
+                         (C01 * rhs[0] + C11 * rhs[1] + C21 * rhs[2]) * idet,
+                         (C02 * rhs[0] + C12 * rhs[1] + C22 * rhs[2]) * idet};
     const double s = leps + (z[0] * u[0] + z[1] * u[1] + z[2] * u[2]);
     // symmetric-matrix entries lambda_T^{mu nu}; off-diagonals counted twice
     lT00 += s * l[0] * l[0] - z[0] * l[0];
