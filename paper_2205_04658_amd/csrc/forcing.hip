@@ -188,7 +188,8 @@ static inline int synth_chunks(int K) { return (K + 8) >> 3; }
 // both components.
 // v_mfma_f32_32x32x16_f16 takes, in lane l, A row l % 32 and B column l % 32
 // with slots 8 (l / 32) .. +7, i.e. (cos, sin) of k = 8 c + 4 (l / 32) .. +3
-// for chunk c: exactly one 16-byte table item each.  Accumulator element i
+// for chunk c: one 16-byte item of each (component, hi | lo) plane of the
+// table and of each hi | lo plane of the twiddles.  Accumulator element i
 // of lane l is block row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
 // Rows and columns past the lattice are clamped on load and skipped on
 // store.  The kernel advances the device step counter when `advance` is set
@@ -202,8 +203,11 @@ static inline int synth_chunks(int K) { return (K + 8) >> 3; }
 // tile, the same; the transposed product with 16-byte stores straight
 // from the accumulators (32-byte pieces per row), 148 us; 32 x 32 tiles
 // (6 waves per SIMD), 49 us; 32 x 128 tiles (1 wave per SIMD), 41 us.
-// Keeping each XCD on its own row bands (below; an XCD's L2 then holds
-// an eighth of the series table) measured the same, and is kept.
+// Re-timed with the contiguous operands and the prefetch: 32 x 32 tiles
+// (5 waves per SIMD) and 2 or 8 wavefronts per workgroup all within 0.3 to
+// 2 us of this form.  Keeping each XCD on its own row bands (below; an
+// XCD's L2 then holds an eighth of the series table) measured the same,
+// and is kept.
 __global__ __launch_bounds__(64 * kSynthWaves) void stir_synth_kernel(
     const uint4* __restrict__ table, const uint4* __restrict__ tw, float* __restrict__ force,
     int64_t force_pitch, int nchunks, int nx, int ny, int row_pitch, float inv_scale,
