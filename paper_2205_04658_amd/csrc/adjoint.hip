@@ -35,6 +35,9 @@ struct Moments {
 template <class DS>
 __device__ __forceinline__ Moments moments_of(const float* f, const float* g, double eps_ref,
                                               double n_ref) {
+  // plane by plane (summed by opposite pairs, as the step kernel does, the
+  // adjoint run measured 1.7 ms slower at 512 x 256: a pair's sum waits for
+  // both of its loads)
   float m00 = 0, m0x = 0, m0y = 0, mxx = 0, mxy = 0, myy = 0, j0 = 0, jx = 0, jy = 0;
   static_for<0, DS::Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
@@ -156,15 +159,19 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   const float Fx = sh.fx + frx;
   const float Fy = sh.fy + fry;
   float q3xxx = 0, q3xxy = 0, q3xyy = 0, q3yyy = 0, q3xzz = 0, q3yzz = 0;
-  static_for<0, Q>([&](auto P) {
+  static_for<0, Q>([&](auto P) {   // odd in v: from f_a - f_b of each pair
     constexpr int p = decltype(P)::value;
-    constexpr double vx = DS::vx[p], vy = DS::vy[p], vz2 = DS::vz2[p];
-    q3xxx += (float)(vx * vx * vx) * f[p];
-    q3xxy += (float)(vx * vx * vy) * f[p];
-    q3xyy += (float)(vx * vy * vy) * f[p];
-    q3yyy += (float)(vy * vy * vy) * f[p];
-    q3xzz += (float)(vx * vz2) * f[p];
-    q3yzz += (float)(vy * vz2) * f[p];
+    constexpr int q = DS::opp[p];
+    if constexpr (q > p) {
+      constexpr double vx = DS::vx[p], vy = DS::vy[p], vz2 = DS::vz2[p];
+      const float d = f[p] - f[q];
+      q3xxx += (float)(vx * vx * vx) * d;
+      q3xxy += (float)(vx * vx * vy) * d;
+      q3xyy += (float)(vx * vy * vy) * d;
+      q3yyy += (float)(vy * vy * vy) * d;
+      q3xzz += (float)(vx * vz2) * d;
+      q3yzz += (float)(vy * vz2) * d;
+    }
   });
   const float M0 = (float)m.T00, M1x = (float)m.T0x, M1y = (float)m.T0y;
 
@@ -172,39 +179,60 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   // per-direction part: lambda of A, B, C, Ag, Bg, u, 1/tau, Phi coefficients
   float lA = 0, lB = 0, lC = 0, lAg = 0, lBg = 0, lux = 0, luy = 0, lu0 = 0, litau = 0;
   float lp0 = 0, lpx = 0, lpy = 0, lpxx = 0, lpxy = 0, lpyy = 0;
+  // By opposite pairs (a, b), v_b = -v_a: s_b = -s_a, the equilibrium
+  // splits into an even part e0 and an odd part e1 in s, and every
+  // accumulation below is the pair's sum (even in v) or difference (odd).
   float mf[Q], mg[Q];
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
-    constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
+    constexpr int q = DS::opp[p];
     constexpr float w = DS::w32[p];
-    const float s = ux * vx + uy * vy;
-    const float om = (u0 - s) * itau;
-    const float feq = w * (ec.A + s * (ec.B + s * ec.C));
-    const float geq = w * (ec.Ag + s * ec.Bg);
-    const float lfp = lf[p], lgp = lg[p];
-    mf[p] = lfp * (1.0f - om);
-    mg[p] = lgp * (1.0f - om);
-    const float lom = -lfp * (f[p] - feq) - lgp * (g[p] - geq);
-    const float lfeq = lfp * om, lgeq = lgp * om;
-    lu0 += lom * itau;
-    litau += lom * (u0 - s);
-    float ls = -lom * itau;
-    lA += w * lfeq;
-    lB += w * s * lfeq;
-    lC += w * s * s * lfeq;
-    ls += w * (ec.B + 2.0f * ec.C * s) * lfeq;
-    lAg += w * lgeq;
-    lBg += w * s * lgeq;
-    ls += w * ec.Bg * lgeq;
-    lux += vx * ls;
-    luy += vy * ls;
-    const float lphi = -w * lfp;
-    lp0 += lphi;
-    lpx += vx * lphi;
-    lpy += vy * lphi;
-    lpxx += vx * vx * lphi;
-    lpxy += vx * vy * lphi;
-    lpyy += vy * vy * lphi;
+    if constexpr (q == p) {   // v_x = v_y = 0: s = 0
+      const float om = u0 * itau;
+      const float lfp = lf[p], lgp = lg[p];
+      mf[p] = lfp * (1.0f - om);
+      mg[p] = lgp * (1.0f - om);
+      const float lom = -lfp * (f[p] - w * ec.A) - lgp * (g[p] - w * ec.Ag);
+      lu0 += lom * itau;
+      litau += lom * u0;
+      lA += w * (lfp * om);
+      lAg += w * (lgp * om);
+      lp0 -= w * lfp;
+    } else if constexpr (q > p) {
+      constexpr float vx = (float)DS::vx[p], vy = (float)DS::vy[p];
+      const float s = ux * vx + uy * vy;
+      const float oma = (u0 - s) * itau, omb = (u0 + s) * itau;
+      const float e0 = w * (ec.A + ec.C * s * s), e1 = w * (ec.B * s);
+      const float g0 = w * ec.Ag, g1 = w * (ec.Bg * s);
+      const float lfa = lf[p], lfb = lf[q], lga = lg[p], lgb = lg[q];
+      mf[p] = lfa * (1.0f - oma);
+      mf[q] = lfb * (1.0f - omb);
+      mg[p] = lga * (1.0f - oma);
+      mg[q] = lgb * (1.0f - omb);
+      const float loma = -lfa * (f[p] - (e0 + e1)) - lga * (g[p] - (g0 + g1));
+      const float lomb = -lfb * (f[q] - (e0 - e1)) - lgb * (g[q] - (g0 - g1));
+      const float los = loma + lomb, lod = loma - lomb;
+      const float lfea = lfa * oma, lfeb = lfb * omb, lgea = lga * oma, lgeb = lgb * omb;
+      const float fs = lfea + lfeb, fd = lfea - lfeb, gs = lgea + lgeb, gd = lgea - lgeb;
+      lu0 += los * itau;
+      litau += u0 * los - s * lod;
+      lA += w * fs;
+      lB += w * s * fd;
+      lC += w * s * s * fs;
+      lAg += w * gs;
+      lBg += w * s * gd;
+      // d/ds of pair member a minus that of b (v_b = -v_a)
+      const float lsd = -lod * itau + w * ec.B * fd + 2.0f * w * ec.C * s * fs + w * ec.Bg * gd;
+      lux += vx * lsd;
+      luy += vy * lsd;
+      const float ps = -w * (lfa + lfb), pd = -w * (lfa - lfb);
+      lp0 += ps;
+      lpx += vx * pd;
+      lpy += vy * pd;
+      lpxx += vx * vx * ps;
+      lpxy += vx * vy * ps;
+      lpyy += vy * vy * ps;
+    }
   });
   // driving-term coefficients (vz^2 folded into p0, pxx, pyy)
   const float lpzz = lp0 - lpxx - lpyy;
@@ -307,16 +335,25 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   const float a00 = (float)lT00, a0x = (float)lT0x, a0y = (float)lT0y;
   const float axx = (float)lTxx, axy = (float)lTxy, ayy = (float)lTyy;
   const float b0 = (float)lJ0, bx = (float)lJx, by = (float)lJy;
-  static_for<0, Q>([&](auto P) {
+  static_for<0, Q>([&](auto P) {   // even part + / - odd part per pair
     constexpr int p = decltype(P)::value;
-    constexpr double vx = DS::vx[p], vy = DS::vy[p], vz2 = DS::vz2[p];
-    const float dm = a00 + (float)vx * a0x + (float)vy * a0y + (float)(vx * vx) * axx +
-                     (float)(vx * vy) * axy + (float)(vy * vy) * ayy +
-                     (float)(vx * vx * vx) * lq3xxx + (float)(vx * vx * vy) * lq3xxy +
-                     (float)(vx * vy * vy) * lq3xyy + (float)(vy * vy * vy) * lq3yyy +
-                     (float)(vx * vz2) * lq3xzz + (float)(vy * vz2) * lq3yzz;
-    put(p, mf[p] + dm);
-    put(Q + p, mg[p] + b0 + (float)vx * bx + (float)vy * by);
+    constexpr int q = DS::opp[p];
+    if constexpr (q == p) {
+      put(p, mf[p] + a00);
+      put(Q + p, mg[p] + b0);
+    } else if constexpr (q > p) {
+      constexpr double vx = DS::vx[p], vy = DS::vy[p], vz2 = DS::vz2[p];
+      const float ev = a00 + (float)(vx * vx) * axx + (float)(vx * vy) * axy + (float)(vy * vy) * ayy;
+      const float od = (float)vx * a0x + (float)vy * a0y + (float)(vx * vx * vx) * lq3xxx +
+                       (float)(vx * vx * vy) * lq3xxy + (float)(vx * vy * vy) * lq3xyy +
+                       (float)(vy * vy * vy) * lq3yyy + (float)(vx * vz2) * lq3xzz +
+                       (float)(vy * vz2) * lq3yzz;
+      const float odg = (float)vx * bx + (float)vy * by;
+      put(p, mf[p] + (ev + od));
+      put(q, mf[q] + (ev - od));
+      put(Q + p, mg[p] + (b0 + odg));
+      put(Q + q, mg[q] + (b0 - odg));
+    }
   });
   // parameter adjoints of this node
   af.x += (double)lFx;
