@@ -83,7 +83,7 @@ __device__ __forceinline__ Pi pi_of(const Moments& m, const Frame& fr) {
 // inside a strip, so that neighbouring tiles, which share halo rows, meet in
 // one L2.  (Row-major order over the XCDs in turn: 1.31x the algorithmic
 // reads at 512 x 256.)
-template <class DS, bool UNIT, bool MASK>
+template <class DS, bool UNIT, bool MASK, bool MU>
 __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   constexpr int Q = DS::Q;
   const int t = (int)(blockIdx.x & 7) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
@@ -102,21 +102,22 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a) {
   const Nbr nb = neighbourhood<Q>(x, y, a.nx, a.ny, a.row);
   const StepShared& sh = a.sh;
 
-  // The first adjoint step has no mu_{t+1}: its transposed pulls then read
-  // the state and are discarded by a select, so that all pulls stay one
-  // branch-free batch of loads (a branch per plane made the compiler wait
-  // for each plane's loads in turn).
-  const bool have_mu = a.mu_in != nullptr;
-  const float* mu = have_mu ? a.mu_in : a.state;
+  // The first adjoint step has no mu_{t+1} (MU = false: lambda = 0, no
+  // transposed pulls); the others pull both in one branch-free batch of
+  // loads (a runtime test per plane made the compiler wait for each
+  // plane's loads in turn).
   float f[Q], g[Q], lf[Q], lg[Q];
   static_for<0, Q>([&](auto P) {
     constexpr int p = decltype(P)::value;
     f[p] = pull<DS, UNIT, p, p, false>(a.state, nb, sh.tap[p]);
     g[p] = pull<DS, UNIT, p, Q + p, false>(a.state, nb, sh.tap[p]);
-    const float mf_in = pull<DS, UNIT, p, p, true>(mu, nb, sh.tap[p]);
-    const float mg_in = pull<DS, UNIT, p, Q + p, true>(mu, nb, sh.tap[p]);
-    lf[p] = have_mu ? mf_in : 0.0f;
-    lg[p] = have_mu ? mg_in : 0.0f;
+    if constexpr (MU) {
+      lf[p] = pull<DS, UNIT, p, p, true>(a.mu_in, nb, sh.tap[p]);
+      lg[p] = pull<DS, UNIT, p, Q + p, true>(a.mu_in, nb, sh.tap[p]);
+    } else {
+      lf[p] = 0.0f;
+      lg[p] = 0.0f;
+    }
   });
   // this node's force and accumulators, loaded with the populations so
   // that their latency overlaps the pulls (the accumulators would otherwise
@@ -509,13 +510,19 @@ __global__ __launch_bounds__(256) void fill_f64_kernel(double* p, size_t n) {
 }
 
 // ---------------------------------------------------------------------------
-template <class DS, bool UNIT>
-static void adj_go(bool mask, const AdjArgs& a, hipStream_t s) {
+template <class DS, bool UNIT, bool MU>
+static void adj_go_mu(bool mask, const AdjArgs& a, hipStream_t s) {
   const dim3 grid(8 * a.tiles_per_xcd);
   if (mask)
-    hipLaunchKernelGGL((adjoint_kernel<DS, UNIT, true>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((adjoint_kernel<DS, UNIT, true, MU>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((adjoint_kernel<DS, UNIT, false>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((adjoint_kernel<DS, UNIT, false, MU>), grid, dim3(256), 0, s, a);
+}
+
+template <class DS, bool UNIT>
+static void adj_go(bool mask, const AdjArgs& a, hipStream_t s) {
+  if (a.mu_in) adj_go_mu<DS, UNIT, true>(mask, a, s);
+  else adj_go_mu<DS, UNIT, false>(mask, a, s);
 }
 
 hipError_t launch_adjoint(int Q, bool unit, bool mask, const AdjArgs& a, hipStream_t s) {
