@@ -218,6 +218,26 @@ def test_force_injection_is_the_change_of_the_totals(full):
         assert abs(d[3]) < 2e-9 * t0[3]
 
 
+def test_force_injection_errors():
+    """The planar set has no driving term (RLB_EUNSUPPORTED) and a batch
+    member's force belongs to its batch (RLB_EINVAL); a lattice without a
+    force injects nothing."""
+    need_gpu()
+    from paper_2205_04658_amd.rlb import Batch, EINVAL, EUNSUPPORTED, RLBError
+    f = workloads.random_fields(64, 16, seed=2)
+    lat = make_lattice(f, 0.7, planar=True)
+    with pytest.raises(RLBError) as e:
+        lat.force_injection()
+    assert e.value.status == EUNSUPPORTED
+    B = Batch([(64, 16), (80, 24)], 0.8)
+    with pytest.raises(RLBError) as e:
+        B[1].force_injection()
+    assert e.value.status == EINVAL
+    B.close()
+    lat = make_lattice(f, 0.7)
+    assert np.array_equal(lat.force_injection(), np.zeros(3))
+
+
 @pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
 def test_shear_wave_1000_steps(full):
     """Shear-wave workload: 64 x 64, tau = 0.8, 1000 steps; every field
