@@ -435,7 +435,9 @@ def run_adjoint(torch, rlb, workloads):
     5 % area (seed 7), tau 0.8, F = 1e-6 x_hat + 32 basis modes (7 <= |k| <=
     9, amplitudes 1e-6); 2000 steps, checkpoint every 100; objective = the
     time-averaged charge current.  Throughput counts forward + backward
-    node-steps (nodes x N) per second of the whole adjoint run."""
+    node-steps (nodes x N) per second of the whole adjoint run, timed with
+    all 20 segments' states resident in HBM (33 GiB, nothing recomputed)
+    and with the minimum of two (3.7 GiB, 18 segments recomputed)."""
     c = workloads.ADJOINT
     nx, ny = c["nx"], c["ny"]
     modes = workloads.stirring_basis(nx, ny, c["nmodes"], c["kmin"], c["kmax"], c["seed"])
@@ -449,27 +451,54 @@ def run_adjoint(torch, rlb, workloads):
         lat.add_disks(discs)
         return lat
 
+    nseg = -(-c["steps"] // c["checkpoint"])
     out = {}
-    for grad in (False, True):
+    # "adjoint": every segment's states resident (nothing recomputed);
+    # "adjoint_recompute": two resident segments, the others recomputed from
+    # their checkpoints while the adjoint sweeps (the minimum memory)
+    for key, grad, resident in (("forward", False, 0), ("adjoint", True, nseg),
+                                ("adjoint_recompute", True, 0)):
         lat = fresh()
-        lat.adjoint_run(4, 2, "current", modes, amps, c["body_force"], grad=grad)   # warm
+        lat.adjoint_run(c["steps"], c["checkpoint"], "current", modes, amps, c["body_force"],
+                        grad=grad, resident=resident)   # warm (and the workspace allocated)
+        lat.close()
         lat = fresh()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         J, g = lat.adjoint_run(c["steps"], c["checkpoint"], "current", modes, amps,
-                               c["body_force"], grad=grad)
+                               c["body_force"], grad=grad, resident=resident)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        out["adjoint" if grad else "forward"] = dict(seconds=wall, mlups=nx * ny * c["steps"] / wall / 1e6)
+        lat.close()
+        out[key] = dict(seconds=wall, mlups=nx * ny * c["steps"] / wall / 1e6)
         if grad:
+            out[key]["resident_segments"] = min(max(resident, 2), nseg)
+            out[key]["workspace_gib"] = adjoint_workspace_bytes(rlb, c, resident) / 2**30
+        if key == "adjoint":
             out["objective"] = J
             out["grad_norm"] = float(np.linalg.norm(g))
             out["dJ_dFb"] = float(g[0])
             out["dJ_dtau"] = float(g[1])
+        elif grad:
+            out[key]["same_gradient"] = bool(J == out["objective"] and
+                                             float(np.linalg.norm(g)) == out["grad_norm"])
     out["workload"] = ("adjoint channel 512x256, 5% discs r=6 (seed 7), tau 0.8, body force 1e-6, "
                        "32 basis modes 7<=|k|<=9 amp 1e-6, N=2000, K=100, objective: mean J^x")
     out["adjoint_vs_forward"] = out["adjoint"]["mlups"] / out["forward"]["mlups"]
     return out
+
+
+def adjoint_workspace_bytes(rlb, c, resident):
+    """Workspace of the adjoint workload's run (rlb_adjoint_workspace_bytes;
+    it does not depend on the number of modes)."""
+    import ctypes
+    lat = rlb.Lattice(c["nx"], c["ny"], c["tau"], walls=True, eps_ref=c["eps"], n_ref=c["n"])
+    cfg = rlb.AdjointCfg(c["steps"], c["checkpoint"], 0, 0, None, None,
+                         c["body_force"], resident)
+    nb = ctypes.c_size_t()
+    rlb.check(rlb.lib().rlb_adjoint_workspace_bytes(lat._h, ctypes.byref(cfg), ctypes.byref(nb)))
+    lat.close()
+    return nb.value
 
 
 def main():

@@ -500,6 +500,12 @@ typedef struct {
   const double* h_modes;   /* host [M][5]: kx, ky (integers), ex, ey, phase    */
   const double* h_amps;    /* host [M]: amplitudes A_m                          */
   double body_force;       /* F_b                                              */
+  int32_t resident;        /* segments of K states kept resident by the
+                              forward pass (the last ones), which the
+                              backward pass then does not recompute; 0 or 1
+                              means the minimum (2, or 1 for a single
+                              segment); values above ceil(N/K) keep all.
+                              The gradient does not depend on it.          */
 } rlb_adjoint_cfg;
 
 /* Set the relaxation time (tau > 1/2) of an existing lattice; this also
@@ -519,10 +525,14 @@ rlb_status rlb_set_relaxation_time(rlb_lattice* lat, double tau);
  * and for batch members. */
 rlb_status rlb_set_relaxation_eta_s(rlb_lattice* lat, double eta_over_s, double dt);
 
-/* Bytes of the adjoint workspace: ceil(N/K) checkpoints + K segment states
- * (twice when there is more than one segment: the next segment is
- * recomputed while the adjoint sweeps the current one) + 2 adjoint states
- * + float64 per-node accumulators. */
+/* Bytes of the adjoint workspace: R resident segments of K states each
+ * (R = cfg->resident clamped to [2, ceil(N/K)], or 1 for a single segment:
+ * a segment that is not resident is recomputed from its checkpoint into a
+ * free segment buffer while the adjoint sweeps the one after it) +
+ * ceil(N/K) - R checkpoints + 2 adjoint states + float64 per-node
+ * accumulators + (K + 2) R launch descriptors (64 bytes each).  With all
+ * segments resident nothing is recomputed: one
+ * state is 2 Q row_stride ny floats (17.8 MB at 512 x 256 with Q = 17). */
 rlb_status rlb_adjoint_workspace_bytes(const rlb_lattice* lat, const rlb_adjoint_cfg* cfg,
                                        size_t* bytes);
 

@@ -70,6 +70,7 @@ rlb_status check_cfg(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
   if (!c) return afail(RLB_EINVAL, "config is null");
   if (c->nsteps < 2 || (c->nsteps & 1)) return afail(RLB_EINVAL, "nsteps must be even and >= 2");
   if (c->checkpoint < 1) return afail(RLB_EINVAL, "checkpoint interval must be >= 1");
+  if (c->resident < 0) return afail(RLB_EINVAL, "resident segments must be >= 0");
   if (c->objective != RLB_OBJ_CURRENT && c->objective != RLB_OBJ_DISSIPATION)
     return afail(RLB_EINVAL, "unknown objective %d", c->objective);
   if (c->nmodes < 0 || c->nmodes > kMaxModesAdj) return afail(RLB_EINVAL, "nmodes must be in [0, 64]");
@@ -92,9 +93,12 @@ AdjLayout adj_layout(const rlb_lattice* lat, const rlb_adjoint_cfg* c) {
   L.state_bytes = align_up((size_t)2 * lat->Q * lat->pitch * sizeof(float));
   L.nseg = (c->nsteps + c->checkpoint - 1) / c->checkpoint;
   const int64_t K = std::min<int64_t>(c->checkpoint, c->nsteps);
+  // segment buffers: at least two when there is more than one segment (one
+  // is recomputed while the adjoint sweeps the other); checkpoints only for
+  // the segments that are not resident
+  L.nbuf = L.nseg > 1 ? std::min<int64_t>(std::max<int64_t>(c->resident, 2), L.nseg) : 1;
   size_t off = 0;
-  L.ck_off = off; off += L.state_bytes * (size_t)L.nseg;
-  L.nbuf = L.nseg > 1 ? 2 : 1;   // recompute buffers
+  L.ck_off = off; off += L.state_bytes * (size_t)(L.nseg - L.nbuf);
   L.store_off = off; off += L.state_bytes * (size_t)K * (size_t)L.nbuf;
   L.mu_off = off; off += 2 * L.state_bytes;
   L.accf_off = off; off += align_up(ncell * sizeof(double2));
@@ -258,7 +262,7 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
   for (int64_t t = 0; t < N; ++t) {
     const int64_t seg = t / K, j = t - seg * K;
     if (seg < kept_from) {
-      if (j == 0)
+      if (j == 0 && h_grad)   // seg < nseg - nbuf: the backward pass recomputes it
         AHIP(hipMemcpyAsync(ck(seg), lat->state[lat->cur], state_copy, hipMemcpyDeviceToDevice, st),
              "checkpoint");
       if (t > N / 2)
@@ -367,8 +371,9 @@ rlb_status rlb_adjoint_run(rlb_lattice* lat, const rlb_adjoint_cfg* cfg, void* d
       }
       AHIP(hipEventRecord(ev_adj[seg & 1], sa), "event record");
       if (seg > 0) {
-        // the buffer of segment seg - 1 was last read by the sweep of seg + 1
-        // (nbuf is 2 whenever there is more than one segment)
+        // the buffer of segment seg - 1 last held segment seg - 1 + nbuf,
+        // swept no later than seg + 1 (nbuf >= 2 whenever there is more
+        // than one segment; the sweep stream runs in order)
         if (seg + 1 < L.nseg) AHIP(hipStreamWaitEvent(st, ev_adj[(seg + 1) & 1], 0), "stream wait");
         if (seg - 1 < kept_from) {
           if (rlb_status s = recompute(seg - 1)) return s;

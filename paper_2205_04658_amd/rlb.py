@@ -65,7 +65,7 @@ class AdjointCfg(ctypes.Structure):
     _fields_ = [("nsteps", ctypes.c_int64), ("checkpoint", ctypes.c_int32),
                 ("objective", ctypes.c_int32), ("nmodes", ctypes.c_int32),
                 ("h_modes", ctypes.c_void_p), ("h_amps", ctypes.c_void_p),
-                ("body_force", ctypes.c_double)]
+                ("body_force", ctypes.c_double), ("resident", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -536,14 +536,17 @@ class Lattice:
         """Per-node tau(x) = 5 (eta/s) / (T(x) dt), T = (pi^2 eps / 3)^(1/4)."""
         check(lib().rlb_set_relaxation_eta_s(self._h, float(eta_over_s), float(dt)))
 
-    def adjoint_run(self, nsteps, checkpoint, objective, modes, amps, body_force, grad=True):
+    def adjoint_run(self, nsteps, checkpoint, objective, modes, amps, body_force, grad=True,
+                    resident=0):
         """Run nsteps from the current state with F = F_b x_hat + sum_m A_m
-        phi_m; return (J, dJ/d(F_b, tau, A_1..A_M) or None)."""
+        phi_m; return (J, dJ/d(F_b, tau, A_1..A_M) or None).  `resident`:
+        segments of `checkpoint` states kept in device memory (0: the
+        minimum; ceil(nsteps / checkpoint) or more: all, nothing recomputed)."""
         torch = _torch()
         modes = np.ascontiguousarray(np.asarray(modes, np.float64).reshape(-1, 5))
         amps = np.ascontiguousarray(np.asarray(amps, np.float64).reshape(-1))
         cfg = AdjointCfg(int(nsteps), int(checkpoint), OBJECTIVES[objective], modes.shape[0],
-                         modes.ctypes.data, amps.ctypes.data, float(body_force))
+                         modes.ctypes.data, amps.ctypes.data, float(body_force), int(resident))
         nb = _sz()
         check(lib().rlb_adjoint_workspace_bytes(self._h, ctypes.byref(cfg), ctypes.byref(nb)))
         ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)

@@ -126,3 +126,21 @@ def test_null_handle_calls(L):
     assert L.rlb_batch_set_open_borders(None, 0.1, 0.0, 0.1, 1.0) == B.EINVAL
     assert L.rlb_set_open_borders(None, 0.1, 0.0, 0.1, 1.0) == B.EINVAL
     assert b"null" in L.rlb_last_error() or len(L.rlb_last_error()) > 0
+
+
+@pytest.mark.parametrize("cls,cname", [(B.AdjointCfg, "rlb_adjoint_cfg"), (B.Params, "rlb_params")])
+def test_binding_structs_match_the_header(cls, cname, tmp_path):
+    """The ctypes structures the binding passes by pointer have the header's
+    size and field offsets (checked with the host C compiler)."""
+    fields = [f for f, _ in cls._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "rlb.h"\nint main(void) {\n'
+                   f'  printf("%zu\\n", sizeof({cname}));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof({cname}, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == [ctypes.sizeof(cls)] + [getattr(cls, f).offset for f in fields]

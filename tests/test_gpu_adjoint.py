@@ -66,6 +66,39 @@ def test_checkpoint_interval_does_not_change_gradient():
         np.testing.assert_array_equal(g, out[0][1])
 
 
+def test_resident_segments_do_not_change_gradient():
+    """Keeping more segments' states resident (fewer recomputed segments,
+    segment buffers reused more than two segments apart, or none recomputed
+    at all) gives the same J and gradient bit for bit; the workspace grows by
+    K - 1 states per extra resident segment (one checkpoint fewer, K states
+    more) plus its K + 2 launch descriptors; a negative count is rejected."""
+    need_gpu()
+    import ctypes
+    from paper_2205_04658_amd import rlb as B
+    K, nseg = 7, -(-N // 7)
+    runs = [(0, 2), (3, 3), (5, 5), (nseg, nseg), (100, nseg)]
+    out, ws = [], []
+    for R, _ in runs:
+        lat = gpu_lattice()
+        out.append(lat.adjoint_run(N, K, "current", MODES, AMPS, FB, resident=R))
+        cfg = B.AdjointCfg(N, K, 0, 0, None, None, FB, R)
+        nb = ctypes.c_size_t()
+        B.check(B.lib().rlb_adjoint_workspace_bytes(lat._h, ctypes.byref(cfg), ctypes.byref(nb)))
+        ws.append(nb.value)
+    for J, g in out[1:]:
+        assert J == out[0][0]
+        np.testing.assert_array_equal(g, out[0][1])
+    q, row, stride, _ = lat.layout()
+    state = -(-stride * NY * 4 // 256) * 256   # one state, 256-byte aligned
+    for (R, nbuf), w in zip(runs, ws):
+        extra = w - ws[0] - (nbuf - 2) * (K - 1) * state
+        assert 0 <= extra <= (nbuf - 2) * (K + 2) * 128 + 256, (R, extra)
+    lat = gpu_lattice()
+    with pytest.raises(B.RLBError) as e:
+        lat.adjoint_run(N, K, "current", MODES, AMPS, FB, resident=-1)
+    assert e.value.status == B.EINVAL
+
+
 @pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
 def test_tile_height_does_not_change_gradient(full):
     """The forward, objective and recompute steps may run at different tile
