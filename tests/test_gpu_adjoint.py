@@ -66,7 +66,8 @@ def test_checkpoint_interval_does_not_change_gradient():
         np.testing.assert_array_equal(g, out[0][1])
 
 
-def test_resident_segments_do_not_change_gradient():
+@pytest.mark.parametrize("full", [False, True], ids=["folded17", "full26"])
+def test_resident_segments_do_not_change_gradient(full):
     """Keeping more segments' states resident (fewer recomputed segments,
     segment buffers reused more than two segments apart, or none recomputed
     at all) gives the same J and gradient bit for bit; the workspace grows by
@@ -79,7 +80,7 @@ def test_resident_segments_do_not_change_gradient():
     runs = [(0, 2), (3, 3), (5, 5), (nseg, nseg), (100, nseg)]
     out, ws = [], []
     for R, _ in runs:
-        lat = gpu_lattice()
+        lat = gpu_lattice(full)
         out.append(lat.adjoint_run(N, K, "current", MODES, AMPS, FB, resident=R))
         cfg = B.AdjointCfg(N, K, 0, 0, None, None, FB, R)
         nb = ctypes.c_size_t()
@@ -93,7 +94,7 @@ def test_resident_segments_do_not_change_gradient():
     for (R, nbuf), w in zip(runs, ws):
         extra = w - ws[0] - (nbuf - 2) * (K - 1) * state
         assert 0 <= extra <= (nbuf - 2) * (K + 2) * 128 + 256, (R, extra)
-    lat = gpu_lattice()
+    lat = gpu_lattice(full)
     with pytest.raises(B.RLBError) as e:
         lat.adjoint_run(N, K, "current", MODES, AMPS, FB, resident=-1)
     assert e.value.status == B.EINVAL
