@@ -693,22 +693,23 @@ def _autograd():
         """J(theta), theta = (F_b, tau, A_1..A_M) as a float64 tensor.  The
         forward resets the lattice to `fields`, runs the step `nsteps` times
         and evaluates the objective; the gradient comes from the library's
-        adjoint run (checkpoint every `checkpoint` steps)."""
+        adjoint run (checkpoint every `checkpoint` steps, `resident` segments
+        kept in device memory)."""
 
         @staticmethod
-        def forward(ctx, theta, lattice, fields, modes, nsteps, checkpoint, objective):
+        def forward(ctx, theta, lattice, fields, modes, nsteps, checkpoint, objective, resident):
             th = theta.detach().cpu().double().numpy()
             lattice.init_fields(fields["eps"], fields["bx"], fields["by"], fields["n"])
             lattice.set_relaxation_time(th[1])
             J, g = lattice.adjoint_run(nsteps, checkpoint, objective, modes, th[2:], th[0],
-                                       grad=True)
+                                       grad=True, resident=resident)
             ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype))
             return torch.tensor(J, dtype=theta.dtype)
 
         @staticmethod
         def backward(ctx, gout):
             (g,) = ctx.saved_tensors
-            return gout * g.to(gout.device), None, None, None, None, None, None
+            return gout * g.to(gout.device), None, None, None, None, None, None, None
 
     return RLBObjective
 
@@ -748,6 +749,9 @@ def power_law_fit(k, y):
     return slope.value, icpt.value
 
 
-def rlb_objective(theta, lattice, fields, modes, nsteps, checkpoint, objective="current"):
-    """Differentiable objective of a driven run (torch.autograd)."""
-    return _autograd().apply(theta, lattice, fields, modes, nsteps, checkpoint, objective)
+def rlb_objective(theta, lattice, fields, modes, nsteps, checkpoint, objective="current",
+                  resident=0):
+    """Differentiable objective of a driven run (torch.autograd); `resident`
+    as in Lattice.adjoint_run."""
+    return _autograd().apply(theta, lattice, fields, modes, nsteps, checkpoint, objective,
+                             resident)

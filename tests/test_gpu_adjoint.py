@@ -144,8 +144,14 @@ def test_autograd_function():
     J.backward()
     lat2 = gpu_lattice()
     Jr, gr = lat2.adjoint_run(N, 7, "current", MODES, AMPS, FB)
-    assert float(J) == Jr
+    assert float(J.detach()) == Jr
     np.testing.assert_array_equal(theta.grad.numpy(), gr)
+    # every segment resident: the same value and gradient
+    theta2 = theta.detach().clone().requires_grad_(True)
+    J2 = rlb_objective(theta2, gpu_lattice(), fields(), MODES, N, 7, "current", 100)
+    J2.backward()
+    assert float(J2.detach()) == Jr
+    np.testing.assert_array_equal(theta2.grad.numpy(), gr)
 
 
 def test_eta_s_relaxation_is_rejected_by_the_adjoint():
