@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % HBM peak, 4096² forced RLB; batched/adjoint vs plain, same GPU"
-KERNEL_SOURCES = ["paper_2205_04658_amd/csrc/step.hip", "paper_2205_04658_amd/csrc/device_common.hpp",
+KERNEL_SOURCES = ["paper_2205_04658_amd/csrc/step.hip", "paper_2205_04658_amd/csrc/step_kernels.hpp",
+                  "paper_2205_04658_amd/csrc/step_cached.hip", "paper_2205_04658_amd/csrc/device_common.hpp",
                   "paper_2205_04658_amd/csrc/forcing.hip",
                   "paper_2205_04658_amd/csrc/dirset.hpp", "paper_2205_04658_amd/csrc/internal.hpp",
                   "paper_2205_04658_amd/csrc/brick.hpp"]

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librlb.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["step.hip", "forcing.hip", "reduce.hip", "boundary.hip", "spectral.hip", "adjoint.hip", "noalloc.hip", "api.cpp",
+SOURCES = ["step.hip", "step_cached.hip", "forcing.hip", "reduce.hip", "boundary.hip", "spectral.hip", "adjoint.hip", "noalloc.hip", "api.cpp",
            "batch_api.cpp", "adjoint_api.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",

@@ -69,10 +69,13 @@ __device__ __forceinline__ float ldp(const float* base, int64_t r, uint32_t c) {
   return *(const gfloat*)(b + c);
 }
 
-template <int PL>
+// NT: a non-temporal store (large lattices); otherwise a plain one, which
+// leaves the value in the last-level cache for the next step's pulls.
+template <int PL, bool NT = true>
 __device__ __forceinline__ void stp(float* base, int64_t r, uint32_t c, float v) {
   gbyte* b = (gbyte*)base + r + PL * 256;
-  __builtin_nontemporal_store(v, (gfloat*)(b + c));
+  if constexpr (NT) __builtin_nontemporal_store(v, (gfloat*)(b + c));
+  else *(gfloat*)(b + c) = v;
 }
 
 // Four-tap interpolation t0 a + t1 b + t2 c + t3 d with t0 + t1 + t2 + t3 = 1,
