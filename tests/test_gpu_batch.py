@@ -347,3 +347,25 @@ def test_batch_record_current_errors_and_empty_runs():
     with pytest.raises(RLBError) as e:
         C.record_current(2, 1)
     assert e.value.status == EUNSUPPORTED
+
+
+def test_store_kind_does_not_change_results():
+    """The step kernels store with plain stores when a launch's two state
+    copies fit in 224 MiB and with non-temporal stores above that: a batch
+    holding a 1024^2 member (285 MB of state, non-temporal) advances its
+    small members bit for bit as the same lattices stepped alone (plain)."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Batch
+    sizes = [(1024, 1024)] + SIZES[:2]
+    B = Batch(sizes, TAU, walls=True)
+    big = workloads.uniform(1024, 1024)
+    B[0].init_fields(big["eps"], big["bx"], big["by"], big["n"])
+    for b, (nx, ny) in enumerate(SIZES[:2]):
+        setup_member(B[b + 1], b, nx, ny)
+    B.set_body_force(*FB)
+    B.step(25)
+    B.sync()
+    ref = single_runs(25)
+    for b in range(2):
+        f, g = B[b + 1].planes()
+        assert torch.equal(f.cpu(), ref[b][0]) and torch.equal(g.cpu(), ref[b][1]), b
