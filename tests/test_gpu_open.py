@@ -88,6 +88,36 @@ def test_open_launch_shapes_are_bitwise_identical():
         assert torch.equal(s, ref), shape
 
 
+def test_border_tiles_first_order():
+    """256 x 64 channel, 1-row tiles: with a strip as wide as the lattice
+    the border tiles run first within each XCD's share (eight whole tile
+    rows each); with 1-tile strips the tiles keep the plain order.  Both
+    give the same state bit for bit, and match the FP64 oracle."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    nx, ny, steps = 256, 64, 30
+    disc = [(90.0, 30.5, 5.0)]
+    f = workloads.random_fields(nx, ny, seed=41, beta=0.01)
+    states = []
+    for shape in [(1, 0, 16), (1, 0, 1)]:
+        lat = Lattice(nx, ny, TAU, open_x=True)
+        lat.set_launch_shape(*shape)
+        lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+        lat.add_disks(np.array(disc))
+        lat.set_open_borders(*BORDERS)
+        lat.step(steps)
+        states.append(lat.save_state().cpu())
+        if len(states) == 1:
+            fields = lat.fields()
+    assert torch.equal(states[0], states[1])
+    solid = geometry.disc_mask(nx, ny, disc)
+    F, G = oracle_start(f)
+    for _ in range(steps):
+        F, G = rlb.step(F, G, TAU, solid=solid, open_x=BORDERS)
+    err = compare(fields, rlb.fields(F, G, solid=solid), scales(beta=0.06, n=0.12))
+    assert max(err.values()) < TOL, err
+
+
 def test_current_series_and_spectrum():
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import power_spectrum
