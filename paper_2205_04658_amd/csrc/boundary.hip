@@ -12,7 +12,7 @@
 // The adjacent columns' frames come from Landau matching of their stored
 // (post-collision) moments.  Streaming stays periodic: the wrapped values
 // reach only the two border columns, which are overwritten.  The step
-// kernel sets the borders itself (open_borders in step.hip, same
+// kernel sets the borders itself (open_borders in step_kernels.hpp, same
 // arithmetic); the kernel here serves widths with nx % 64 == 1, where the
 // outlet column and column nx-2 fall in different 64-node tiles.
 #include <algorithm>
