@@ -99,7 +99,9 @@ def test_border_tiles_first_order():
     disc = [(90.0, 30.5, 5.0)]
     f = workloads.random_fields(nx, ny, seed=41, beta=0.01)
     states = []
-    for shape in [(1, 0, 16), (1, 0, 1)]:
+    # one workgroup per tile and a persistent grid (4 per CU), both in the
+    # border-first order; then 1-tile strips (plain order)
+    for shape in [(1, 0, 16), (1, 4, 16), (2, 4, 32), (1, 0, 1)]:
         lat = Lattice(nx, ny, TAU, open_x=True)
         lat.set_launch_shape(*shape)
         lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
@@ -109,7 +111,8 @@ def test_border_tiles_first_order():
         states.append(lat.save_state().cpu())
         if len(states) == 1:
             fields = lat.fields()
-    assert torch.equal(states[0], states[1])
+    for st in states[1:]:
+        assert torch.equal(states[0], st)
     solid = geometry.disc_mask(nx, ny, disc)
     F, G = oracle_start(f)
     for _ in range(steps):
