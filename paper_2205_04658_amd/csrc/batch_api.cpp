@@ -42,6 +42,10 @@ struct rlb_batch {
   LaunchShape shape;
   int ntiles;
   int table_rows;          // tile_rows the table was built for (0 = none)
+  // (first tile, tiles) of consecutive members whose state fits the
+  // last-level cache; a captured graph steps each group through all its
+  // steps before the next
+  std::vector<std::pair<int32_t, int32_t>> groups;
   int64_t rec_rows;        // rows of all members (recorded current density)
   double fx, fy;
   int64_t step;
@@ -136,6 +140,21 @@ rlb_status build_tables(rlb_batch* B, int tile_rows) {
     begin += n;
   }
   B->ntiles = begin;
+  B->groups.clear();
+  {
+    const double per_tile = 2.0 * 64 * tile_rows * 2 * B->Q * sizeof(float);
+    int first = 0, count = 0;
+    for (int b = 0; b < B->count; ++b) {
+      const int n = tiles_of(B->h_desc[b].nx, B->h_desc[b].ny, tile_rows);
+      if (count > 0 && (double)(count + n) * per_tile > kCachedStateBytes) {
+        B->groups.emplace_back(first, count);
+        first += count;
+        count = 0;
+      }
+      count += n;
+    }
+    if (count > 0) B->groups.emplace_back(first, count);
+  }
   BHIP(hipMemcpyAsync(B->d_desc, B->h_desc.data(), sizeof(LatDesc) * B->count,
                       hipMemcpyHostToDevice, B->stream), "upload descriptors");
   BHIP(hipMemcpyAsync(B->d_tile_lat, B->h_tile_lat.data(), sizeof(int32_t) * B->ntiles,
@@ -181,9 +200,14 @@ TileArgs tile_args(const rlb_batch* B, int parity) {
 // rec: J^x of column rec_x of every member, written row by row (see
 // records_current) into rec[rec_row + y]
 hipError_t launch_batch_step(const rlb_batch* B, int parity, bool mask, int force,
-                             double* rec = nullptr, int rec_x = 0) {
+                             double* rec = nullptr, int rec_x = 0, int tile_first = 0,
+                             int tiles = -1) {
   const int mode = (B->p.flags & RLB_OPEN_X) ? MODE_OPEN : MODE_STEP;
   TileArgs a = tile_args(B, parity);
+  if (tiles >= 0) {   // one group of members
+    a.tile_first = tile_first;
+    a.ntiles = tiles;
+  }
   a.sh.rec = rec;
   a.sh.rec_x = rec_x;
   return launch_tiles(B->Q, stream_mode(B->p.cfl), mask, mode, force, a, B->shape, B->num_cu,
@@ -380,8 +404,16 @@ rlb_status rlb_batch_step(rlb_batch* B, int64_t nsteps) {
       drop_graph(B);   // a graph whose instantiation failed
       BHIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal), "begin capture");
       hipError_t e = hipSuccess;
-      for (int k = 0; k < B->graph_steps && e == hipSuccess; ++k)
-        e = launch_batch_step(B, k & 1, mask, force);
+      if (B->groups.size() > 1) {
+        // group by group: each group's state stays in the last-level cache
+        // through its graph_steps steps (the members are independent)
+        for (const auto& g : B->groups)
+          for (int k = 0; k < B->graph_steps && e == hipSuccess; ++k)
+            e = launch_batch_step(B, k & 1, mask, force, nullptr, 0, g.first, g.second);
+      } else {
+        for (int k = 0; k < B->graph_steps && e == hipSuccess; ++k)
+          e = launch_batch_step(B, k & 1, mask, force);
+      }
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(B->stream, &g);
       if (e != hipSuccess || e2 != hipSuccess) {

@@ -73,6 +73,14 @@ struct LatDesc {
                           // (0 alone; a batch's members follow each other)
 };
 
+// A step launch whose two state copies take at most this many bytes fits
+// the 256 MB last-level cache: its kernels store with plain stores (the
+// next step reads the state from that cache), larger launches with
+// non-temporal ones (measured crossover between 214 MB, plain faster, and
+// 285 MB, non-temporal faster).  Batches step members in groups of this
+// size inside a captured graph.
+constexpr double kCachedStateBytes = 224.0 * 1024 * 1024;
+
 struct TileArgs {
   StepShared sh;
   const LatDesc* lats;

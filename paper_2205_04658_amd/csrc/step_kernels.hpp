@@ -15,10 +15,6 @@
 
 namespace rlb {
 
-// both state copies at most this many bytes: plain stores (measured
-// crossover between 214 MB, plain faster, and 285 MB, non-temporal faster)
-constexpr double kCachedStateBytes = 224.0 * 1024 * 1024;
-
 // The plain-store launch (step_cached.hip): arguments as launch_tiles after
 // the tile height and grid are fixed.
 hipError_t launch_tiles_cached(int Q, int sm, bool mask, int mode, int force_mode,
