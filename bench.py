@@ -248,8 +248,8 @@ def run_plain(torch, rlb, workloads, layout, steps, warmup, shape=None, eta_s=No
 def run_batch(torch, rlb, workloads, steps, warmup):
     """The batched channel workload: 64 lattices W ~ U{256..2048} x
     H ~ U{128..512}, bounce-back walls, discs of radius 6 at 1/5/10 % area,
-    body force 1e-6 along x, tau 0.8, one launch per step over all lattices,
-    replayed from a hipGraph."""
+    body force 1e-6 along x, tau 0.8, replayed from a hipGraph that steps
+    each cache-sized group of lattices through all its steps in turn."""
     c = workloads.CHANNELS
     lats = workloads.channel_batch(c["count"], c["seed"], c["wmin"], c["wmax"], c["hmin"],
                                    c["hmax"], c["radius"], c["fractions"])
