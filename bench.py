@@ -249,7 +249,9 @@ def run_batch(torch, rlb, workloads, steps, warmup):
     """The batched channel workload: 64 lattices W ~ U{256..2048} x
     H ~ U{128..512}, bounce-back walls, discs of radius 6 at 1/5/10 % area,
     body force 1e-6 along x, tau 0.8, replayed from a hipGraph that steps
-    each cache-sized group of lattices through all its steps in turn."""
+    each cache-sized group of lattices through all its 64 steps in turn
+    (the warmup captures the graph; steps past the last whole graph are
+    direct launches, also group by group)."""
     c = workloads.CHANNELS
     lats = workloads.channel_batch(c["count"], c["seed"], c["wmin"], c["wmax"], c["hmin"],
                                    c["hmax"], c["radius"], c["fractions"])
@@ -554,7 +556,7 @@ def main():
         variants["planar12"]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
     batched = None
     if not a.no_batch:
-        batched = run_batch(torch, rlb, workloads, max(a.steps // 5, 50), 20)
+        batched = run_batch(torch, rlb, workloads, max(a.steps // 5, 50), 128)
         batched["vs_plain"] = batched["mlups"] / main_run["mlups"]
     part2 = None
     if not a.no_part2:

@@ -465,8 +465,13 @@ rlb_status rlb_batch_info(const rlb_batch* batch, int32_t* count, int64_t* cells
 
 /* Launch shape (as rlb_set_launch_shape, except that a batch of the full
  * set keeps tile_rows 4) and autotuner (as rlb_autotune) of the batched
- * step; graph replay of steps_per_graph (even, 0 = off, default 16) steps
- * per launch. */
+ * step; graph replay of steps_per_graph (even, 0 = off, default 64) steps
+ * per launch.  Members whose state together exceeds 224 MiB are stepped in
+ * consecutive groups of at most that size, each group through all the
+ * steps of a graph (or of one rlb_batch_step call's direct launches)
+ * before the next, so that a group's state stays in the last-level cache;
+ * the first step of each group reads it from HBM, so longer graphs pay
+ * that read less often. */
 rlb_status rlb_batch_set_launch_shape(rlb_batch* batch, int32_t tile_rows, int32_t grid_per_cu,
                                       int32_t strip);
 rlb_status rlb_batch_get_launch_shape(const rlb_batch* batch, int32_t* tile_rows,

@@ -43,8 +43,8 @@ struct rlb_batch {
   int ntiles;
   int table_rows;          // tile_rows the table was built for (0 = none)
   // (first tile, tiles) of consecutive members whose state fits the
-  // last-level cache; a captured graph steps each group through all its
-  // steps before the next
+  // last-level cache; a captured graph, and a run of direct steps, steps
+  // each group through all its steps before the next
   std::vector<std::pair<int32_t, int32_t>> groups;
   int64_t rec_rows;        // rows of all members (recorded current density)
   double fx, fy;
@@ -271,7 +271,7 @@ rlb_status rlb_batch_create(const rlb_params* p, int32_t count, const int32_t* h
   B->ws_bytes = bytes;
   B->stream = (hipStream_t)hip_stream;
   B->shape = LaunchShape{4, 0, 16};
-  B->graph_steps = 16;
+  B->graph_steps = 64;
   for (int b = 0; b < count; ++b) B->rec_rows += h_ny[b];
   for (int b = 0; b < count; ++b) {
     rlb_params q = *p;
@@ -431,6 +431,15 @@ rlb_status rlb_batch_step(rlb_batch* B, int64_t nsteps) {
       advance(B, B->graph_steps);
       left -= B->graph_steps;
     }
+  }
+  if (left > 1 && B->groups.size() > 1) {
+    // direct launches, group by group as in the graph
+    for (const auto& g : B->groups)
+      for (int64_t k = 0; k < left; ++k)
+        BHIP(launch_batch_step(B, (int)((parity + k) & 1), mask, force, nullptr, 0, g.first,
+                               g.second), "batch step");
+    advance(B, left);
+    left = 0;
   }
   while (left > 0) {
     BHIP(launch_batch_step(B, parity, mask, force), "batch step");

@@ -674,7 +674,7 @@ class Batch:
         check(lib().rlb_batch_autotune(self._h, int(trials), out, 64))
         return _tune_rows(out)
 
-    def use_graph(self, steps_per_graph=16):
+    def use_graph(self, steps_per_graph=64):
         check(lib().rlb_batch_use_graph(self._h, int(steps_per_graph)))
 
     def timing(self, enable=True):

@@ -349,15 +349,20 @@ def test_batch_record_current_errors_and_empty_runs():
     assert e.value.status == EUNSUPPORTED
 
 
-def test_store_kind_does_not_change_results():
+@pytest.mark.parametrize("graph", [16, 0], ids=["graph", "direct"])
+def test_store_kind_does_not_change_results(graph):
     """The step kernels store with plain stores when a launch's two state
     copies fit in 224 MiB and with non-temporal stores above that: a batch
     holding a 1024^2 member (285 MB of state, non-temporal) advances its
-    small members bit for bit as the same lattices stepped alone (plain)."""
+    small members bit for bit as the same lattices stepped alone (plain).
+    The 1024^2 member makes a group of its own, so the batch steps two
+    groups in turn: from a graph (16 steps) then by direct launches (9),
+    or by direct launches only."""
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import Batch
     sizes = [(1024, 1024)] + SIZES[:2]
     B = Batch(sizes, TAU, walls=True)
+    B.use_graph(graph)
     big = workloads.uniform(1024, 1024)
     B[0].init_fields(big["eps"], big["bx"], big["by"], big["n"])
     for b, (nx, ny) in enumerate(SIZES[:2]):
@@ -369,3 +374,12 @@ def test_store_kind_does_not_change_results():
     for b in range(2):
         f, g = B[b + 1].planes()
         assert torch.equal(f.cpu(), ref[b][0]) and torch.equal(g.cpu(), ref[b][1]), b
+    from paper_2205_04658_amd.rlb import Lattice
+    lat = Lattice(1024, 1024, TAU, walls=True)
+    lat.init_fields(big["eps"], big["bx"], big["by"], big["n"])
+    lat.set_body_force(*FB)
+    lat.step(25)
+    lat.sync()
+    f, g = B[0].planes()
+    f1, g1 = lat.planes()
+    assert torch.equal(f, f1) and torch.equal(g, g1)
