@@ -287,12 +287,14 @@ def run_batch(torch, rlb, workloads, steps, warmup):
     return out
 
 
-def run_part2_sweep(torch, rlb, workloads, steps=1000, warmup=50):
+def run_part2_sweep(torch, rlb, workloads, steps=1000, warmup=128):
     """The Part II placement sweep as one batch: six 1024 x 256 channels
     (the single impurity, and the pair at each of the five separations
-    1.68 ... 8.39 um, 25 degrees), shared inlet/outlet and tau, one launch
-    per step over all six, replayed from a hipGraph; then the same number
-    of steps recording each channel's j(t) (one column launch per step)."""
+    1.68 ... 8.39 um, 25 degrees), shared inlet/outlet and tau, replayed
+    from 64-step hipGraphs that step each cache-sized group of channels
+    (three) through all 64 steps in turn (the warmup captures the graph);
+    then the same number of steps recording each channel's j(t), one
+    launch over all six and one column launch per step."""
     c = workloads.PART2
     nx, ny = c["nx"], c["ny"]
     placements = [workloads.part2_discs()] + [workloads.part2_discs(d) for d in c["separations_um"]]
