@@ -356,8 +356,10 @@ def test_store_kind_does_not_change_results(graph):
     holding a 1024^2 member (285 MB of state, non-temporal) advances its
     small members bit for bit as the same lattices stepped alone (plain).
     The 1024^2 member makes a group of its own, so the batch steps two
-    groups in turn: from a graph (16 steps) then by direct launches (9),
-    or by direct launches only."""
+    groups in turn. One step first leaves the batch on its second state
+    copy; the next 24 steps then take one step to realign, a 16-step graph
+    and 7 direct steps group by group, or 24 direct steps group by group
+    starting from the second copy."""
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import Batch
     sizes = [(1024, 1024)] + SIZES[:2]
@@ -368,9 +370,12 @@ def test_store_kind_does_not_change_results(graph):
     for b, (nx, ny) in enumerate(SIZES[:2]):
         setup_member(B[b + 1], b, nx, ny)
     B.set_body_force(*FB)
-    B.step(25)
+    B.step(1)
+    B.step(24)
     B.sync()
     ref = single_runs(25)
+    for b in range(3):
+        assert B[b].step_count == 25, b
     for b in range(2):
         f, g = B[b + 1].planes()
         assert torch.equal(f.cpu(), ref[b][0]) and torch.equal(g.cpu(), ref[b][1]), b
