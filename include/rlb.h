@@ -429,7 +429,9 @@ rlb_status rlb_batch_set_open_borders(rlb_batch* batch, double bx, double by, do
 
 /* Advance every member nsteps steps.  All members must be at the same
  * ping-pong phase (they are unless a member was re-initialised alone):
- * otherwise RLB_ESTATE. */
+ * otherwise RLB_ESTATE.  Members may be advanced group by group (see
+ * rlb_batch_use_graph), so after RLB_EDEVICE from a launch the members'
+ * states and step counts are undefined; re-initialise them. */
 rlb_status rlb_batch_step(rlb_batch* batch, int64_t nsteps);
 
 /* Bytes of the rlb_batch_record_current workspace that holds `chunk` steps
