@@ -80,6 +80,9 @@ def test_init_fields_match():
 CASES = {
     "periodic": dict(),
     "cfl_half": dict(cfl=0.5),
+    # the smallest cfl = dt/dx of the paper's runs (Ch. 4 "Model and Methods":
+    # dt = 0.05 with node spacings 0.04 ... 0.32): 0.05 / 0.32 = 0.15625
+    "cfl_0_15625_stir": dict(cfl=0.15625, stir=(2.0, 4.5, 2e-4, 13)),
     "body_force": dict(body=(2e-4, -1e-4)),
     "stirring": dict(stir=(2.0, 4.5, 2e-4, 11)),
     "walls_discs": dict(walls=True, discs=[(20.5, 17.0, 6.0), (60.2, 25.7, 4.0)], body=(1e-4, 0.0)),
