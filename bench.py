@@ -551,6 +551,11 @@ def main():
         variants["cfl_1_25"] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms",
                                                   "bytes_per_cell", "achieved_gbs")}
         variants["cfl_1_25"]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
+        # the paper's smallest time step, cfl = 0.05 / 0.32 (one-cell interpolating pull)
+        v = run_plain(torch, rlb, workloads, a.layout, max(a.steps // 3, 10), a.warmup, cfl=0.15625)
+        variants["cfl_0_15625"] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms",
+                                                     "bytes_per_cell", "achieved_gbs")}
+        variants["cfl_0_15625"]["hbm_frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
         # planar (2+1) momentum set, 4096^2 seeded random flow (no driving term)
         v = run_plain(torch, rlb, workloads, "planar12", max(a.steps // 3, 10), a.warmup)
         variants["planar12"] = {k: v[k] for k in ("mlups", "ms_per_step", "kernel_ms",
