@@ -523,7 +523,7 @@ def main():
                     help="tile_rows,grid_per_cu,strip: fixed launch shape instead of the autotuner")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library steps a lattice on one GPU (no multi-GPU path is implemented); --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2205_04658_amd import rlb, workloads
