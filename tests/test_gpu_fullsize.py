@@ -79,7 +79,7 @@ def at(planes, xs, ys, torch):
                   torch.tensor(xs, device=planes.device)].double().cpu().numpy()
 
 
-def sampled_step_error(lat, xs, ys, tau, force_at, full, eps_ref, n_ref, solid=None):
+def sampled_step_error(lat, xs, ys, tau, force_at, full, eps_ref, n_ref, solid=None, cfl=1.0):
     """Take one GPU step of `lat`; return (max error F, max error G, largest
     one-step change) of the sampled nodes against the oracle patch step."""
     import torch
@@ -104,7 +104,7 @@ def sampled_step_error(lat, xs, ys, tau, force_at, full, eps_ref, n_ref, solid=N
         sp = None
         if solid is not None:
             sp = solid[(ys[m] + np.arange(-1, 2))[:, None] % ny, (xs[m] + np.arange(-1, 2))[None, :] % nx]
-        Fn, Gn = rlb.step(F, G, tau, force=fo, solid=sp)
+        Fn, Gn = rlb.step(F, G, tau, cfl=cfl, force=fo, solid=sp)
         want_f = to_library(Fn[:, 1:2, 1:2], order, q, eps_ref)[:, 0, 0]
         want_g = to_library(Gn[:, 1:2, 1:2], order, q, n_ref)[:, 0, 0]
         err_f = max(err_f, np.abs(got_f[:, m] - want_f).max())
@@ -114,13 +114,17 @@ def sampled_step_error(lat, xs, ys, tau, force_at, full, eps_ref, n_ref, solid=N
     return err_f, err_g, change
 
 
-@pytest.mark.parametrize("start,full", [("rest", False), ("random", False), ("random", True)],
-                         ids=["workload_rest", "random_flow", "random_flow_full26"])
-def test_headline_step_sampled(start, full):
+@pytest.mark.parametrize("start,full,cfl", [("rest", False, 1.0), ("random", False, 1.0),
+                                            ("random", True, 1.0), ("random", False, 0.15625)],
+                         ids=["workload_rest", "random_flow", "random_flow_full26",
+                              "random_flow_cfl_0_15625"])
+def test_headline_step_sampled(start, full, cfl):
+    """The 4096^2 stirred workload in the launch shape bench.py times, and
+    at the paper's smallest cfl (0.05 / 0.32, timed as a variant)."""
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import Lattice
     eps_ref, n_ref = C["eps"], C["n"]
-    lat = Lattice(N, N, C["tau"], full26=full, eps_ref=eps_ref, n_ref=n_ref)
+    lat = Lattice(N, N, C["tau"], cfl=cfl, full26=full, eps_ref=eps_ref, n_ref=n_ref)
     if start == "rest":
         f = workloads.uniform(N, N, eps_ref, n_ref)
     else:
@@ -134,7 +138,8 @@ def test_headline_step_sampled(start, full):
     lat.step(t0)
     xs, ys = samples()
     force = forcing.Stirring(N, N, *stir).field_at(t0, xs, ys)   # (2, M)
-    ef, eg, change = sampled_step_error(lat, xs, ys, C["tau"], force, full, eps_ref, n_ref)
+    ef, eg, change = sampled_step_error(lat, xs, ys, C["tau"], force, full, eps_ref, n_ref,
+                                        cfl=cfl)
     assert ef < TOL and eg < TOL, (ef, eg)
     assert change > 10 * TOL          # the step moved the sampled populations
 
