@@ -114,13 +114,15 @@ def sampled_step_error(lat, xs, ys, tau, force_at, full, eps_ref, n_ref, solid=N
     return err_f, err_g, change
 
 
-@pytest.mark.parametrize("start,full,cfl", [("rest", False, 1.0), ("random", False, 1.0),
-                                            ("random", True, 1.0), ("random", False, 0.15625)],
-                         ids=["workload_rest", "random_flow", "random_flow_full26",
-                              "random_flow_cfl_0_15625"])
-def test_headline_step_sampled(start, full, cfl):
+@pytest.mark.parametrize("start,full,cfl,eta_s", [
+    ("rest", False, 1.0, None), ("random", False, 1.0, None), ("random", True, 1.0, None),
+    ("random", False, 0.15625, None), ("random", False, 1.0, (0.007, 0.05))],
+    ids=["workload_rest", "random_flow", "random_flow_full26", "random_flow_cfl_0_15625",
+         "random_flow_eta_s"])
+def test_headline_step_sampled(start, full, cfl, eta_s):
     """The 4096^2 stirred workload in the launch shape bench.py times, and
-    at the paper's smallest cfl (0.05 / 0.32, timed as a variant)."""
+    its two single-lattice variants that keep a 3 x 3 pull: the paper's
+    smallest cfl (0.05 / 0.32) and per-node tau from eta/s."""
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import Lattice
     eps_ref, n_ref = C["eps"], C["n"]
@@ -133,12 +135,16 @@ def test_headline_step_sampled(start, full, cfl):
     del f
     stir = (C["kmin"], C["kmax"], C["amplitude"], C["seed"])
     lat.set_stirring(*stir)
+    tau = C["tau"]
+    if eta_s is not None:
+        lat.set_relaxation_eta_s(*eta_s)
+        tau = rlb.ViscosityRelaxation(*eta_s)
     lat.set_launch_shape(*((4, 0, 16) if full else (2, 0, 16)))
     t0 = 20
     lat.step(t0)
     xs, ys = samples()
     force = forcing.Stirring(N, N, *stir).field_at(t0, xs, ys)   # (2, M)
-    ef, eg, change = sampled_step_error(lat, xs, ys, C["tau"], force, full, eps_ref, n_ref,
+    ef, eg, change = sampled_step_error(lat, xs, ys, tau, force, full, eps_ref, n_ref,
                                         cfl=cfl)
     assert ef < TOL and eg < TOL, (ef, eg)
     assert change > 10 * TOL          # the step moved the sampled populations
