@@ -66,9 +66,9 @@ def to_library(F, order, q, ref):
     return out
 
 
-def gather(planes, xs, ys, nx, ny, torch):
-    """(Q, M, 3, 3) float64 patches around (xs, ys), periodic."""
-    d = torch.tensor([-1, 0, 1], device=planes.device)
+def gather(planes, xs, ys, nx, ny, torch, r=1):
+    """(Q, M, 2r+1, 2r+1) float64 patches around (xs, ys), periodic."""
+    d = torch.arange(-r, r + 1, device=planes.device)
     iy = (torch.tensor(ys, device=planes.device)[:, None, None] + d[None, :, None]) % ny
     ix = (torch.tensor(xs, device=planes.device)[:, None, None] + d[None, None, :]) % nx
     return planes[:, iy, ix].double().cpu().numpy()
@@ -84,8 +84,9 @@ def sampled_step_error(lat, xs, ys, tau, force_at, full, eps_ref, n_ref, solid=N
     one-step change) of the sampled nodes against the oracle patch step."""
     import torch
     nx, ny = lat.nx, lat.ny
+    r = 2 if cfl > 1 else 1        # the two-cell stencil pulls from a 5 x 5 patch
     F0, G0 = lat.planes()
-    pf, pg = gather(F0, xs, ys, nx, ny, torch), gather(G0, xs, ys, nx, ny, torch)
+    pf, pg = gather(F0, xs, ys, nx, ny, torch, r), gather(G0, xs, ys, nx, ny, torch, r)
     del F0, G0
     lat.step(1)
     lat.sync()
@@ -98,31 +99,35 @@ def sampled_step_error(lat, xs, ys, tau, force_at, full, eps_ref, n_ref, solid=N
     for m in range(len(xs)):
         F = to_oracle(pf[:, m], order, eps_ref)
         G = to_oracle(pg[:, m], order, n_ref)
-        fo = np.zeros((3, 3, 3))
+        w = 2 * r + 1
+        fo = np.zeros((3, w, w))
         if force_at is not None:
-            fo[0, 1, 1], fo[1, 1, 1] = force_at[0, m], force_at[1, m]
+            fo[0, r, r], fo[1, r, r] = force_at[0, m], force_at[1, m]
         sp = None
         if solid is not None:
-            sp = solid[(ys[m] + np.arange(-1, 2))[:, None] % ny, (xs[m] + np.arange(-1, 2))[None, :] % nx]
+            sp = solid[(ys[m] + np.arange(-r, r + 1))[:, None] % ny,
+                       (xs[m] + np.arange(-r, r + 1))[None, :] % nx]
         Fn, Gn = rlb.step(F, G, tau, cfl=cfl, force=fo, solid=sp)
-        want_f = to_library(Fn[:, 1:2, 1:2], order, q, eps_ref)[:, 0, 0]
-        want_g = to_library(Gn[:, 1:2, 1:2], order, q, n_ref)[:, 0, 0]
+        want_f = to_library(Fn[:, r:r + 1, r:r + 1], order, q, eps_ref)[:, 0, 0]
+        want_g = to_library(Gn[:, r:r + 1, r:r + 1], order, q, n_ref)[:, 0, 0]
         err_f = max(err_f, np.abs(got_f[:, m] - want_f).max())
         err_g = max(err_g, np.abs(got_g[:, m] - want_g).max())
-        change = max(change, np.abs(want_f - pf[:, m, 1, 1]).max())
+        change = max(change, np.abs(want_f - pf[:, m, r, r]).max())
     print(f"max |gpu - oracle|: F {err_f:.3e}  G {err_g:.3e}; one-step change {change:.3e}")
     return err_f, err_g, change
 
 
 @pytest.mark.parametrize("start,full,cfl,eta_s", [
     ("rest", False, 1.0, None), ("random", False, 1.0, None), ("random", True, 1.0, None),
-    ("random", False, 0.15625, None), ("random", False, 1.0, (0.007, 0.05))],
+    ("random", False, 0.15625, None), ("random", False, 1.25, None),
+    ("random", False, 1.0, (0.007, 0.05))],
     ids=["workload_rest", "random_flow", "random_flow_full26", "random_flow_cfl_0_15625",
-         "random_flow_eta_s"])
+         "random_flow_cfl_1_25", "random_flow_eta_s"])
 def test_headline_step_sampled(start, full, cfl, eta_s):
     """The 4096^2 stirred workload in the launch shape bench.py times, and
-    its two single-lattice variants that keep a 3 x 3 pull: the paper's
-    smallest cfl (0.05 / 0.32) and per-node tau from eta/s."""
+    its single-lattice variants: the paper's smallest and largest cfl
+    (0.05 / 0.32 and 0.05 / 0.04, the latter a 5 x 5 pull) and per-node
+    tau from eta/s."""
     torch = need_gpu()
     from paper_2205_04658_amd.rlb import Lattice
     eps_ref, n_ref = C["eps"], C["n"]
