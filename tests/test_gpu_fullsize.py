@@ -19,9 +19,9 @@ import os
 import numpy as np
 import pytest
 
-from oracle import forcing, geometry, rlb
+from oracle import forcing, geometry, planar, rlb
 from paper_2205_04658_amd import workloads
-from rlbtest import _folded_dirs, _full_dirs, need_gpu
+from rlbtest import _folded_dirs, _full_dirs, need_gpu, scales
 
 pytestmark = pytest.mark.gpu
 
@@ -182,6 +182,43 @@ def test_widest_rows_step_sampled(full):
     ef, eg, change = sampled_step_error(lat, xs, ys, 0.6, force, full, eps_ref, n_ref)
     assert ef < TOL and eg < TOL, (ef, eg)
     assert change > 10 * TOL
+
+
+def test_planar_step_sampled():
+    """The planar (2+1) set on the 4096^2 seeded random flow that bench.py
+    times: one GPU step from the initial fields, then the fields at sampled
+    nodes against the oracle's planar step of a 5 x 5 patch of the same
+    float32 fields (a step, then the fields' own pull: two cells)."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    f = workloads.random_fields(N, N, seed=C["seed"], beta=0.01)
+    lat = Lattice(N, N, C["tau"], planar=True, eps_ref=C["eps"], n_ref=C["n"])
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    lat.step(1)
+    lat.sync()
+    xs, ys = samples()
+    g = lat.fields()
+    names = ("eps", "beta_x", "beta_y", "n")
+    got = {k: g[k][torch.tensor(ys, device=g[k].device), torch.tensor(xs, device=g[k].device)]
+           .double().cpu().numpy() for k in names}
+    del g
+    sc = scales(beta=0.05)
+    worst = dict.fromkeys(names, 0.0)
+    change = 0.0
+    for m in range(len(xs)):
+        iy = (ys[m] + np.arange(-2, 3))[:, None] % N
+        ix = (xs[m] + np.arange(-2, 3))[None, :] % N
+        F, G = planar.initial_state(*(f[k][iy, ix].astype(np.float64) for k in ("eps", "bx", "by", "n")))
+        o0 = planar.fields(F, G)
+        F, G = planar.step(F, G, C["tau"])
+        o = planar.fields(F, G)
+        for k in names:
+            worst[k] = max(worst[k], abs(got[k][m] - o[k][2, 2]) / sc[k])
+            change = max(change, abs(o[k][2, 2] - o0[k][2, 2]) / sc[k])
+    print(f"planar 4096^2, max scaled field error over {len(xs)} nodes: {worst}; "
+          f"one-step change {change:.3e}")
+    assert max(worst.values()) < 1e-5, worst
+    assert change > 1e-4              # the step moved the sampled fields
 
 
 def test_forced_1024_step_sampled_after_200_steps():
