@@ -6,8 +6,11 @@ around sampled nodes, the FP64 oracle steps each patch (with its solid
 nodes), and the patch centre is compared with the GPU's state after the
 step.  Samples include lattice corners (periodic wrap), both sides of
 64-node tile edges, wall rows and random nodes.  Covered: the forced 4096^2
-headline (from rest, from a random flow, full set), the forced 1024^2 run
-after 200 steps, and members of the 64-channel batch.  The adjoint at
+headline (from rest, from a random flow, full set) and its variants (cfl
+0.15625 and 1.25, the latter from 5 x 5 patches; per-node tau from eta/s;
+the planar set, by its fields), the forced 1024^2 run after 200 steps, and
+members of the 64-channel batch.  The 1024 x 256 Part II channel is small
+enough for the oracle to run whole, every node compared.  The adjoint at
 512 x 256 over 2000 steps is checked through properties that hold at any
 size: its gradient along a random direction against a central difference
 of its own forward objective, and invariance under the checkpoint
@@ -21,7 +24,7 @@ import pytest
 
 from oracle import forcing, geometry, planar, rlb
 from paper_2205_04658_amd import workloads
-from rlbtest import _folded_dirs, _full_dirs, need_gpu, scales
+from rlbtest import _folded_dirs, _full_dirs, compare, need_gpu, scales
 
 pytestmark = pytest.mark.gpu
 
@@ -219,6 +222,41 @@ def test_planar_step_sampled():
           f"one-step change {change:.3e}")
     assert max(worst.values()) < 1e-5, worst
     assert change > 1e-4              # the step moved the sampled fields
+
+
+def test_part2_channel_full_size():
+    """The Part II channel at its full 1024 x 256 size: two discs 3.38 um
+    apart, velocity inlet and pressure outlet, in the launch shape the
+    autotuner picks for it (8-row tiles).  Small enough for the oracle to
+    run whole: after 4 steps from the inlet flow every node's fields,
+    the border columns and the solid nodes included, against it."""
+    torch = need_gpu()
+    from paper_2205_04658_amd.rlb import Lattice
+    c = workloads.PART2
+    nx, ny = c["nx"], c["ny"]
+    discs = workloads.part2_discs(3.38)
+    borders = (c["beta_in"], 0.0, c["n"], c["eps_out"])
+    f = workloads.uniform(nx, ny, c["eps"], c["n"])
+    f["bx"][:] = c["beta_in"]
+    lat = Lattice(nx, ny, c["tau"], open_x=True, eps_ref=c["eps"], n_ref=c["n"])
+    lat.init_fields(f["eps"], f["bx"], f["by"], f["n"])
+    lat.add_disks(np.array(discs))
+    lat.set_open_borders(*borders)
+    lat.set_launch_shape(8, 0, 16)
+    steps = 4
+    lat.step(steps)
+    lat.sync()
+    solid = geometry.disc_mask(nx, ny, discs)
+    F, G = rlb.initial_state(*(f[k].astype(np.float64) for k in ("eps", "bx", "by", "n")))
+    for _ in range(steps):
+        F, G = rlb.step(F, G, c["tau"], solid=solid, open_x=borders)
+    o = rlb.fields(F, G, solid=solid)
+    g = lat.fields()
+    err = compare(g, o, scales(beta=0.1, n=0.1))
+    print(f"Part II 1024 x 256 after {steps} steps, max scaled field error: {err}")
+    assert max(err.values()) < 1e-5, err
+    # the step moved the flow: the discs' wakes and the borders
+    assert np.abs(o["beta_y"]).max() > 1e-3
 
 
 def test_forced_1024_step_sampled_after_200_steps():
